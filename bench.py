@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark: ALS-NCG on the MovieLens-20M-shaped synthetic problem, one GPU.
+
+Workload: 138,493 users x 26,744 items, exactly 20,000,263 ratings (Zipf item
+popularity, log-normal user activity, half-star values from a planted rank-50
+model), n_f = 100, lambda = 0.05, FP32 factors, FP64 reductions.  All inputs
+are seeded and resident in HBM before the timed region.
+
+One step = one full ALS-NCG iteration (Algorithm 2): quartic coefficients
+(one pass over R), backtracking on the device, x += alpha p, the ALS
+preconditioner P(x) = two half-sweeps (U block of the gradient fused into
+the U half-sweep), the M block of the gradient (one pass over R^T), and the
+direction update.  value = half-sweep ratings per second sustained by the
+whole iteration: 2 * nnz * steps / elapsed.
+
+Prints one JSON line (rank 0).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ALS half-sweep ratings/s + time-to-f-tol, ALS-NCG vs ALS; fold-in p99 ms"
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sweep_flops(nnz, n_rows, n_f):
+    """Algorithmic flops of one half-sweep: symmetric Gram n_f(n_f+1) and RHS
+    2 n_f per rating, Cholesky n_f^3/3 and two triangular solves 2 n_f^2 per row."""
+    return nnz * (n_f * (n_f + 1) + 2 * n_f) + n_rows * (n_f ** 3 / 3.0 + 2 * n_f ** 2)
+
+
+def cpu_baseline(P, target_s=15.0):
+    """The FP64 oracle's U half-sweep on a bounded sample of user rows."""
+    import numpy as np
+
+    import oracle
+    import synth
+    threads = oracle.set_threads(0)
+    rng = np.random.default_rng(123)
+    order = rng.permutation(P.n_u)
+    counts = P.R.counts()
+
+    def sample(k_ratings):
+        cum = np.cumsum(counts[order])
+        k = int(np.searchsorted(cum, k_ratings)) + 1
+        rows = np.sort(order[:k])
+        ind = [P.R.indices[P.R.indptr[r]:P.R.indptr[r + 1]] for r in rows]
+        val = [P.R.values[P.R.indptr[r]:P.R.indptr[r + 1]] for r in rows]
+        ip = np.zeros(k + 1, np.int64)
+        np.cumsum([a.size for a in ind], out=ip[1:])
+        return synth.Csr(k, P.n_m, ip, np.concatenate(ind), np.concatenate(val)), k
+
+    M = P.M0.astype(np.float32).astype(np.float64)
+    sub, k = sample(100_000)
+    t = time.perf_counter()
+    oracle.half_sweep(sub, M, P.lam)
+    dt = time.perf_counter() - t
+    rate = sub.nnz / max(dt, 1e-9)
+    want = int(min(P.nnz, max(200_000, rate * target_s)))
+    sub, k = sample(want)
+    t = time.perf_counter()
+    oracle.half_sweep(sub, M, P.lam)
+    dt = time.perf_counter() - t
+    return {"value": sub.nnz / dt, "unit": "ratings/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle U half-sweep (Eq. 3) over %d random user rows = %d ratings "
+                      "of the same matrix, n_f=%d, %.1f s" % (k, sub.nnz, P.n_f, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design "
+              "is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1508_03110_amd.solver import AlsNcg, Context, DeviceProblem
+
+    t0 = time.perf_counter()
+    P = synth.c1_ml20m()
+    log("generated %s: %d x %d, nnz=%d in %.1f s" % (P.name, P.n_u, P.n_m, P.nnz, time.perf_counter() - t0))
+    ctx = Context(0)
+    DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32)
+    infoR, infoRt = DP.R.info(), DP.Rt.info()
+    log("plans: R", infoR, "R^T", infoRt)
+    U0 = P.U0.astype(np.float32)
+    M0 = P.M0.astype(np.float32)
+    solver = AlsNcg(DP).init(U0, M0)
+    for _ in range(args.warmup):
+        solver.step()
+    log("warmup done: f=%.10g alpha=%s trials=%d" % (solver.f, solver.alpha, solver.n_trials))
+
+    solver.enable_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        solver.step()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    elapsed = t2 - t1
+    ms_step = elapsed / args.steps * 1e3
+    phases = solver.phase_ms()
+    log("timed %d steps: %.3f ms/step, phases %s, f=%.10g" % (args.steps, ms_step, phases, solver.f))
+
+    fU = sweep_flops(P.nnz, P.n_u, P.n_f)
+    fM = sweep_flops(P.nnz, P.n_m, P.n_f)
+    tU = phases["sweep_U"] * 1e-3
+    tM = phases["sweep_M"] * 1e-3
+    achieved = fU / tU / 1e12
+    roofline = {"bound": "mfma", "kernel": "sweep_chunks_kernel<float,7> (U half-sweep, one launch)",
+                "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": fU, "launch_ms": round(phases["sweep_U"], 4)}
+    # streaming passes: algorithmic bytes (index+value per rating, factor rows read once, output)
+    by_coef = P.nnz * 8 + (P.n_u + P.n_m) * P.n_f * 4 * 2 + (P.n_u + 1 + P.n_m + 1) * 8
+    by_grad = P.nnz * 8 + (P.n_u + P.n_m) * P.n_f * 4 + P.n_m * P.n_f * 4 + (P.n_m + 1) * 8
+    result = {
+        "metric": METRIC,
+        "value": 2.0 * P.nnz * args.steps / elapsed,
+        "unit": "ratings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ALS-NCG iteration, MovieLens-20M-shaped synthetic ratings",
+                   "n_u": P.n_u, "n_m": P.n_m, "nnz": P.nnz, "n_f": P.n_f, "lambda": P.lam,
+                   "value_def": "2*nnz half-sweep ratings per ALS-NCG iteration / iteration time"},
+        "half_sweep_ratings_per_s": {"U": P.nnz / tU, "M": P.nnz / tM},
+        "phase_ms": {k: round(v, 4) for k, v in phases.items()},
+        "sweep_tflops": {"U": fU / tU / 1e12, "M": fM / tM / 1e12},
+        "pass_hbm_gbs": {"linesearch_coeffs": by_coef / (phases["linesearch_coeffs"] * 1e-3) / 1e9,
+                         "gradient_M": by_grad / (phases["gradient_M"] * 1e-3) / 1e9},
+        "roofline": roofline,
+        "f": solver.f,
+        "gnorm_over_N": solver.gnorm() / (P.n_f * (P.n_u + P.n_m)),
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        result["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * alsncg.h -- C ABI of the MI355X (gfx950) ALS / ALS-NCG hot path.
+ *
+ * Method: Winlaw, Hynes, Caterini, De Sterck, "Algorithmic Acceleration of
+ * Parallel ALS for Collaborative Filtering" (arXiv:1508.03110).  Section
+ * II defines the loss (Eq. (1)); Section III-A the ALS row solves (Eq. (3),
+ * Eq. (4), Algorithm 1); Section III-B ALS-NCG (Eq. (5), Eq. (8),
+ * Algorithm 2); Section V-C the one-pass quartic line search (Algorithm 4)
+ * and the gradient.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller unless a
+ *    parameter name ends in _host.  The library never frees, and never
+ *    keeps, a caller pointer after the call returns.
+ *  - Every compute call is asynchronous and stream-ordered on `stream` (a
+ *    hipStream_t passed as void*; NULL = the default stream).  Outputs are
+ *    valid once the stream has been synchronised.  Argument errors are
+ *    detected on the host before anything is enqueued and reported through
+ *    the return code; nothing is thrown across the ABI and nothing aborts.
+ *  - A context holds workspace and is not thread-safe: use one context per
+ *    host thread / stream.  Calls on one context must be issued on one stream
+ *    (its workspace is reused call after call).
+ *  - Factors are row-major: U is [n_u, ld], M is [n_m, ld], ld >= n_f; row i
+ *    holds the n_f latent factors of user (or item) i (the paper's n_f x n
+ *    column-per-entity matrices, same memory image).  Padding columns
+ *    n_f..ld-1 are never read and never written.
+ *  - The concatenated unknown x of Eq. (5) is one buffer [U; M] of
+ *    n_u*ld + n_m*ld elements, so U = x and M = x + n_u*ld.
+ *  - Ratings: one orientation of R as CSR (int64 indptr [n_rows+1], int32
+ *    column ids [nnz], float values [nnz]); the item orientation is the CSR
+ *    of R^T.  Column ids inside a row must be distinct.  Rating values are
+ *    FP32 in every path (half-stars are exact); the FP64 path widens them.
+ *  - Regularisation is always the paper's count-weighted lambda * n_i of
+ *    Eq. (1) (n_i = number of ratings of row i); lambda >= 0.
+ *  - Element type of factor and vector arguments is selected by `dt`:
+ *    ALS_F64 (double), ALS_F32 (float).  ALS_BF16 is reserved.
+ */
+#ifndef ALSNCG_H
+#define ALSNCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ALS_API __attribute__((visibility("default")))
+#else
+#define ALS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { ALS_F64 = 0, ALS_F32 = 1, ALS_BF16 = 2 } als_dtype;
+
+typedef enum {
+    ALS_OK = 0,
+    ALS_E_INVAL = -1,      /* bad argument (NULL pointer, size, unsupported n_f / dtype) */
+    ALS_E_HIP = -2,        /* a HIP runtime call failed */
+    ALS_E_NOT_SPD = -3,    /* a row's normal equations were not positive definite */
+    ALS_E_NONFINITE = -4,  /* reserved */
+    ALS_E_NOMEM = -5,      /* device allocation failed */
+    ALS_E_BUDGET = -6      /* request larger than the stated limit */
+} als_status;
+
+typedef struct als_ctx als_ctx;
+typedef struct als_plan als_plan;
+
+/* One orientation of the ratings matrix (device arrays). */
+typedef struct {
+    int64_t n_rows;          /* rows of this orientation (users for R, items for R^T) */
+    int64_t n_cols;          /* columns (items for R, users for R^T) */
+    int64_t nnz;             /* number of ratings */
+    const int64_t *indptr;   /* device [n_rows + 1], indptr[0] = 0, non-decreasing */
+    const int32_t *indices;  /* device [nnz], column ids in [0, n_cols), distinct per row */
+    const float *values;     /* device [nnz], ratings */
+} als_csr;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  Returns ALS_OK and *out, or an
+ * error code with *out = NULL. */
+ALS_API int als_ctx_create(als_ctx **out, int device);
+/* Release the context and its workspace (synchronises the device first).
+ * NULL is ignored. */
+ALS_API void als_ctx_destroy(als_ctx *ctx);
+/* Text of a status code (static storage). */
+ALS_API const char *als_strerror(int status);
+/* Bytes of device workspace currently held by the context. */
+ALS_API size_t als_ctx_workspace_bytes(const als_ctx *ctx);
+
+/* ---------------------------------------------------------------- row plan
+ *
+ * Work decomposition of one orientation of R, built once before the
+ * iteration loop (the ratings are static, as the paper's routing tables are,
+ * Section V-B): rows are cut into chunks of at most `chunk` ratings, chunks
+ * are ordered longest first, and rows longer than `chunk` are marked for a
+ * split-K second stage with a fixed-order reduction (results do not depend
+ * on scheduling).  chunk = 0 picks a size from the matrix shape.  The call
+ * copies R->indptr to the host (it synchronises the device) and allocates
+ * the plan's device arrays; the plan stays valid until als_plan_destroy and
+ * may only be used with a CSR of the same indptr.
+ */
+ALS_API int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **out);
+ALS_API void als_plan_destroy(als_plan *plan);
+/* Plan statistics: out[0]=n_rows, [1]=nnz, [2]=n_chunks, [3]=split rows,
+ * [4]=split chunks, [5]=chunk size, [6]=longest row. */
+ALS_API int als_plan_info(const als_plan *plan, int64_t out[7]);
+
+/* ---------------------------------------------------------------- hot path */
+
+/*
+ * ALS half-sweep, Eq. (3) (Eq. (4) when R is the CSR of R^T; Algorithm 1
+ * runs one half-sweep per orientation).  For every row i of R with n_i > 0:
+ *     A_i = sum_{j in I_i} y_j y_j^T + lambda n_i I,   v_i = sum_{j in I_i} r_ij y_j,
+ *     X[i] = A_i^{-1} v_i   (Cholesky factorisation, Section V-B),
+ * where y_j = Y[j] is a row of the fixed factor Y [R->n_cols, ld].  Rows with
+ * n_i = 0 get X[i] = 0.  X [R->n_rows, ld] is overwritten.
+ *   grad_out (may be NULL): [R->n_rows, ld]; receives 2 (A_i x_i - v_i)
+ *     with x_i = X_at[i], i.e. the gradient block of Eq. (1) for the rows of
+ *     R at the point (X_at, Y) (Section V-C), taken from the same Gram
+ *     matrices at no extra pass.  X_at (may be NULL: the contents of X before
+ *     this call) is [R->n_rows, ld] and may not overlap grad_out.  Rows with
+ *     n_i = 0 get 0.
+ *   bad_row (may be NULL): device int64; set to the smallest row whose A_i
+ *     was not numerically SPD, or INT64_MAX when every row was SPD.  Such
+ *     rows are written as NaN.
+ * n_f: 1..143 for ALS_F32, 1..95 for ALS_F64.  Y and X must not overlap.
+ */
+ALS_API int als_sweep(als_ctx *ctx, const als_plan *plan, const als_csr *R, const void *Y, void *X,
+                      int n_f, int ld, double lambda, als_dtype dt, const void *X_at,
+                      void *grad_out, int64_t *bad_row, void *stream);
+
+/*
+ * Gradient of Eq. (1) (Section III-A; Section V-C, gradient evaluation):
+ *   g_ui = 2 lambda n_ui u_i + 2 sum_{j in I_i} m_j (u_i^T m_j - r_ij),
+ *   g_mj = 2 lambda n_mj m_j + 2 sum_{i in I_j} u_i (u_i^T m_j - r_ij),
+ * by one pass over R (U block) and one over R^T (M block).  gU [n_u, ld] /
+ * gM [n_m, ld] may each be NULL to skip that block.  out2 (device double
+ * [2], may be NULL): out2[0] = f(U, M) of Eq. (1), out2[1] = ||gU||^2 +
+ * ||gM||^2 over the blocks requested; both reduced in FP64 in a fixed order.
+ * When out2 is given both passes run (f needs the data term of the R pass
+ * and the item regulariser of the R^T pass) even if gU or gM is NULL.
+ */
+ALS_API int ncg_gradient(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, const als_plan *plan_Rt,
+                 const als_csr *Rt, const void *U, const void *M, int n_f, int ld, double lambda,
+                 als_dtype dt, void *gU, void *gM, double *out2, void *stream);
+
+/*
+ * Coefficients of the line-search quartic (Section V-C): with
+ * u_i = U[i] + alpha pU[i] and m_j = M[j] + alpha pM[j],
+ *     f(x + alpha p) = sum_{n=0..4} coeffs[n] alpha^n,
+ * computed in ONE pass over the ratings of R (user-major, gathering the item
+ * side), per-rating dot products in the factor type and all accumulation in
+ * FP64 (fixed reduction order).  coeffs: device double [5].  The item
+ * regulariser needs the item counts n_mj, taken from Rt->indptr (Rt is the
+ * CSR of R^T; only its indptr is read).  coeffs[1] equals g^T p.
+ */
+ALS_API int linesearch_coeffs(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, const als_csr *Rt,
+                      const void *U, const void *M, const void *pU, const void *pM, int n_f,
+                      int ld, double lambda, als_dtype dt, double *coeffs, void *stream);
+
+/*
+ * Backtracking line search, Algorithm 4, evaluated on the device from the
+ * quartic coefficients (no data pass): alpha = alpha0 tau^n for the first
+ * n = 0, 1, ..., max_trials-1 with
+ *     (1 - c) C1 + alpha (C2 + alpha (C3 + alpha C4)) <= 0,
+ * which is f(x + alpha p) - f(x) <= alpha c g^T p divided by alpha > 0.
+ * alpha_out (device double): the step, or 0 when no trial passed or C1 >= 0
+ * (not a descent direction); trials_out (device int32, may be NULL): n, or
+ * -1 on failure.  Section V-C uses tau = 0.9, c = 0.5, alpha0 = 10.
+ */
+ALS_API int ncg_backtrack(als_ctx *ctx, const double *coeffs, double alpha0, double tau, double c,
+                  int max_trials, double *alpha_out, int32_t *trials_out, void *stream);
+
+/*
+ * x <- x + alpha p over n elements, alpha read from device memory (Algorithm
+ * 2, x_{k+1} = x_k + alpha_k p_k).  The FP32 path forms x + alpha p in FP64
+ * and rounds once.
+ */
+ALS_API int ncg_axpy(als_ctx *ctx, int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,
+             void *stream);
+
+/*
+ * y <- a x + b y over n elements with host scalars a, b (FP64 arithmetic,
+ * one rounding).  Used by Algorithm 2's restarts: p = -gbar (a = -1, b = 0)
+ * and the ALS step x = x - gbar = P(x) (a = -1, b = 1).  With b = 0 the old
+ * contents of y are not read.
+ */
+ALS_API int ncg_axpby(als_ctx *ctx, int64_t n, double a, const void *x, double b, void *y,
+                      als_dtype dt, void *stream);
+
+/*
+ * Preconditioned direction update of Algorithm 2 with beta of Eq. (8), over
+ * the flat vectors of Eq. (5) (n elements each):
+ *     gbar_new = x - xbar                 (xbar = P(x), one ALS iteration)
+ *     beta     = gbar_new^T (g_new - g_old) / den     (den = gbar_old^T g_old)
+ *     p        <- -gbar_new + beta p
+ * and the FP64 scalars scal (device double [4], read and written):
+ *     in : scal[0] = den of the previous iteration
+ *     out: scal[0] = gbar_new^T g_new (the next den), scal[1] = beta,
+ *          scal[2] = ||g_new||^2, scal[3] = gbar_new^T (g_new - g_old).
+ * beta is 0 when restart != 0 (p = -gbar_new, the start p_0 = -gbar_0 of
+ * Algorithm 2), when den is 0 or not finite, or when beta is not finite;
+ * pr_plus != 0 clamps beta at 0.  g_old may be NULL when restart != 0.
+ * xbar is overwritten with gbar_new.
+ */
+ALS_API int ncg_direction(als_ctx *ctx, int64_t n, const void *x, void *xbar, const void *g_new,
+                  const void *g_old, void *p, double *scal, int restart, int pr_plus,
+                  als_dtype dt, void *stream);
+
+/*
+ * Fold-in: a batch of n_req new users, each solved against the FIXED item
+ * factors M [n_items, ld] by the row solve of Eq. (3):
+ *     U_out[q] = (M_I^T M_I + lambda n_q I)^{-1} M_I^T r_q,
+ * for request q with ratings (req_items, req_vals)[req_indptr[q] ..
+ * req_indptr[q+1]) (device arrays).  Each request is independent: its result
+ * does not depend on the other requests in the batch.  req_status (device
+ * int32 [n_req], may be NULL): 0, ALS_E_INVAL for an empty request (output
+ * 0), ALS_E_NOT_SPD (output NaN).  One wavefront solves one request.
+ */
+ALS_API int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int ld, double lambda,
+            als_dtype dt, int64_t n_req, const int64_t *req_indptr, const int32_t *req_items,
+            const float *req_vals, void *U_out, int32_t *req_status, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ALSNCG_H */

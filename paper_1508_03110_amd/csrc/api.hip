@@ -1,0 +1,322 @@
+// C ABI of libalsncg: context, workspace, row plans and the argument checks
+// in front of every kernel launch.  The declarations and their contracts are
+// in include/alsncg.h.
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace alsncg {
+
+void *Ctx::workspace(size_t bytes, hipStream_t stream, int *err) {
+    if (bytes == 0) bytes = 256;
+    if (bytes <= ws_bytes) return ws;
+    if (ws) {
+        // earlier launches on this stream may still read the old buffer
+        if (hipStreamSynchronize(stream) != hipSuccess) {
+            *err = ALS_E_HIP;
+            return nullptr;
+        }
+        (void)hipFree(ws);
+        ws = nullptr;
+        ws_bytes = 0;
+    }
+    const size_t want = align_up(bytes + bytes / 4, 1 << 20);
+    if (hipMalloc(&ws, want) != hipSuccess) {
+        ws = nullptr;
+        *err = ALS_E_NOMEM;
+        return nullptr;
+    }
+    ws_bytes = want;
+    return ws;
+}
+
+static bool dtype_ok(als_dtype dt, int n_f, bool sweep) {
+    if (n_f < 1) return false;
+    if (dt == ALS_F32) return sweep ? n_f <= 143 : n_f <= 144;
+    if (dt == ALS_F64) return sweep ? n_f <= 95 : n_f <= 144;
+    return false;
+}
+
+static bool csr_ok(const als_csr *R) {
+    if (!R || R->n_rows < 0 || R->n_cols < 0 || R->nnz < 0) return false;
+    if (R->n_rows > INT32_MAX || R->n_cols > INT32_MAX) return false;
+    if (!R->indptr) return false;
+    if (R->nnz > 0 && (!R->indices || !R->values)) return false;
+    return true;
+}
+
+static bool plan_matches(const Plan *p, const als_csr *R) {
+    return p && p->n_rows == R->n_rows && p->nnz == R->nnz;
+}
+
+static bool lambda_ok(double lambda) { return lambda >= 0.0 && isfinite(lambda); }
+
+template <typename V>
+static int upload(V **dst, const std::vector<V> &src) {
+    *dst = nullptr;
+    const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(V);
+    if (hipMalloc((void **)dst, bytes) != hipSuccess) {
+        *dst = nullptr;
+        return ALS_E_NOMEM;
+    }
+    if (!src.empty() && hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice) != hipSuccess)
+        return ALS_E_HIP;
+    return ALS_OK;
+}
+
+}  // namespace alsncg
+
+using namespace alsncg;
+
+extern "C" {
+
+const char *als_strerror(int status) {
+    switch (status) {
+        case ALS_OK: return "ok";
+        case ALS_E_INVAL: return "invalid argument";
+        case ALS_E_HIP: return "HIP runtime error";
+        case ALS_E_NOT_SPD: return "normal equations not positive definite";
+        case ALS_E_NONFINITE: return "non-finite value";
+        case ALS_E_NOMEM: return "device allocation failed";
+        case ALS_E_BUDGET: return "request exceeds the stated limit";
+        default: return "unknown status";
+    }
+}
+
+int als_ctx_create(als_ctx **out, int device) {
+    if (!out) return ALS_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return ALS_E_HIP;
+    if (device < 0 || device >= n) return ALS_E_INVAL;
+    if (hipSetDevice(device) != hipSuccess) return ALS_E_HIP;
+    als_ctx *c = new (std::nothrow) als_ctx();
+    if (!c) return ALS_E_NOMEM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cu = prop.multiProcessorCount;
+    *out = c;
+    return ALS_OK;
+}
+
+void als_ctx_destroy(als_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    delete ctx;
+}
+
+size_t als_ctx_workspace_bytes(const als_ctx *ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+void als_plan_destroy(als_plan *p) {
+    if (!p) return;
+    void *bufs[] = {p->chunk_row, p->chunk_begin, p->chunk_len, p->chunk_slot,
+                    p->split_row, p->split_slot0, p->split_nslot};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+int als_plan_info(const als_plan *p, int64_t out[7]) {
+    if (!p || !out) return ALS_E_INVAL;
+    out[0] = p->n_rows;
+    out[1] = p->nnz;
+    out[2] = p->n_chunks;
+    out[3] = p->n_split_rows;
+    out[4] = p->n_slots;
+    out[5] = p->chunk;
+    out[6] = p->max_row;
+    return ALS_OK;
+}
+
+int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **out) {
+    if (!out) return ALS_E_INVAL;
+    *out = nullptr;
+    if (!ctx || !csr_ok(R) || chunk < 0) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    const int64_t n = R->n_rows;
+    std::vector<int64_t> ip((size_t)n + 1);
+    if (hipDeviceSynchronize() != hipSuccess) return ALS_E_HIP;
+    if (hipMemcpy(ip.data(), R->indptr, ip.size() * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return ALS_E_HIP;
+    if (ip[0] != 0 || ip[(size_t)n] != R->nnz) return ALS_E_INVAL;
+    int64_t max_row = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t len = ip[i + 1] - ip[i];
+        if (len < 0 || len > R->n_cols) return ALS_E_INVAL;
+        max_row = std::max(max_row, len);
+    }
+    if (chunk == 0) {
+        // at most the average work of one resident wavefront slot (8 per CU):
+        // longer rows are split so that no single wave dominates the launch
+        const int64_t slots = (int64_t)ctx->num_cu * 8;
+        chunk = std::max<int64_t>(256, (R->nnz + slots - 1) / slots);
+        chunk = (chunk + 3) / 4 * 4;
+    }
+    chunk = std::min<int64_t>(chunk, INT32_MAX / 2);
+    std::vector<int32_t> crow, clen, cslot, srow, sslot0, snslot;
+    std::vector<int64_t> cbeg;
+    int64_t slots = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t len = ip[i + 1] - ip[i];
+        const int64_t nck = len <= chunk ? 1 : (len + chunk - 1) / chunk;
+        if (nck == 1) {
+            crow.push_back((int32_t)i);
+            cbeg.push_back(ip[i]);
+            clen.push_back((int32_t)len);
+            cslot.push_back(-1);
+            continue;
+        }
+        int64_t per = (len + nck - 1) / nck;
+        per = (per + 3) / 4 * 4;
+        const int64_t s0 = slots;
+        int32_t ns = 0;
+        for (int64_t o = 0; o < len; o += per) {
+            crow.push_back((int32_t)i);
+            cbeg.push_back(ip[i] + o);
+            clen.push_back((int32_t)std::min(per, len - o));
+            cslot.push_back((int32_t)(slots++));
+            ++ns;
+        }
+        srow.push_back((int32_t)i);
+        sslot0.push_back((int32_t)s0);
+        snslot.push_back(ns);
+    }
+    if (slots > INT32_MAX) return ALS_E_INVAL;
+    // longest chunks first: the hardware dispatcher then schedules greedily
+    std::vector<int64_t> order(crow.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return clen[a] > clen[b]; });
+    std::vector<int32_t> crow2(order.size()), clen2(order.size()), cslot2(order.size());
+    std::vector<int64_t> cbeg2(order.size());
+    for (size_t k = 0; k < order.size(); ++k) {
+        crow2[k] = crow[order[k]];
+        cbeg2[k] = cbeg[order[k]];
+        clen2[k] = clen[order[k]];
+        cslot2[k] = cslot[order[k]];
+    }
+    als_plan *p = new (std::nothrow) als_plan();
+    if (!p) return ALS_E_NOMEM;
+    p->n_rows = n;
+    p->nnz = R->nnz;
+    p->n_chunks = (int64_t)crow2.size();
+    p->n_split_rows = (int64_t)srow.size();
+    p->n_slots = slots;
+    p->chunk = chunk;
+    p->max_row = max_row;
+    int rc = ALS_OK;
+    if (rc == ALS_OK) rc = upload(&p->chunk_row, crow2);
+    if (rc == ALS_OK) rc = upload(&p->chunk_begin, cbeg2);
+    if (rc == ALS_OK) rc = upload(&p->chunk_len, clen2);
+    if (rc == ALS_OK) rc = upload(&p->chunk_slot, cslot2);
+    if (rc == ALS_OK) rc = upload(&p->split_row, srow);
+    if (rc == ALS_OK) rc = upload(&p->split_slot0, sslot0);
+    if (rc == ALS_OK) rc = upload(&p->split_nslot, snslot);
+    if (rc != ALS_OK) {
+        als_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return ALS_OK;
+}
+
+int als_sweep(als_ctx *ctx, const als_plan *plan, const als_csr *R, const void *Y, void *X,
+              int n_f, int ld, double lambda, als_dtype dt, const void *X_at, void *grad_out,
+              int64_t *bad_row, void *stream) {
+    if (!ctx || !csr_ok(R) || !plan_matches(plan, R) || !X || ld < n_f || !lambda_ok(lambda) ||
+        !dtype_ok(dt, n_f, true))
+        return ALS_E_INVAL;
+    if (!Y && R->nnz > 0) return ALS_E_INVAL;
+    if (Y == X) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    if (grad_out && (grad_out == X || grad_out == X_at || grad_out == Y)) return ALS_E_INVAL;
+    return launch_sweep(ctx, plan, R, Y, X, n_f, ld, lambda, dt, X_at, grad_out, bad_row,
+                        (hipStream_t)stream);
+}
+
+int ncg_gradient(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, const als_plan *plan_Rt,
+                 const als_csr *Rt, const void *U, const void *M, int n_f, int ld, double lambda,
+                 als_dtype dt, void *gU, void *gM, double *out2, void *stream) {
+    if (!ctx || !csr_ok(R) || !csr_ok(Rt) || !plan_matches(plan_R, R) ||
+        !plan_matches(plan_Rt, Rt) || !U || !M || ld < n_f || !lambda_ok(lambda) ||
+        !dtype_ok(dt, n_f, false))
+        return ALS_E_INVAL;
+    if (R->n_rows != Rt->n_cols || R->n_cols != Rt->n_rows || R->nnz != Rt->nnz) return ALS_E_INVAL;
+    if (!gU && !gM && !out2) return ALS_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_gradient(ctx, plan_R, R, plan_Rt, Rt, U, M, n_f, ld, lambda, dt, gU, gM, out2,
+                           (hipStream_t)stream);
+}
+
+int linesearch_coeffs(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, const als_csr *Rt,
+                      const void *U, const void *M, const void *pU, const void *pM, int n_f,
+                      int ld, double lambda, als_dtype dt, double *coeffs, void *stream) {
+    if (!ctx || !csr_ok(R) || !Rt || !Rt->indptr || !plan_matches(plan_R, R) || !U || !M ||
+        !pU || !pM || !coeffs || ld < n_f || !lambda_ok(lambda) || !dtype_ok(dt, n_f, false))
+        return ALS_E_INVAL;
+    if (Rt->n_rows != R->n_cols) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_coeffs(ctx, plan_R, R, Rt, U, M, pU, pM, n_f, ld, lambda, dt, coeffs,
+                         (hipStream_t)stream);
+}
+
+int ncg_backtrack(als_ctx *ctx, const double *coeffs, double alpha0, double tau, double c,
+                  int max_trials, double *alpha_out, int32_t *trials_out, void *stream) {
+    if (!ctx || !coeffs || !alpha_out || !(alpha0 > 0.0) || !(tau > 0.0 && tau < 1.0) ||
+        !(c > 0.0 && c < 1.0) || max_trials < 1)
+        return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_backtrack(coeffs, alpha0, tau, c, max_trials, alpha_out, trials_out,
+                            (hipStream_t)stream);
+}
+
+int ncg_axpy(als_ctx *ctx, int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,
+             void *stream) {
+    if (!ctx || n < 0 || (n > 0 && (!x || !p)) || !alpha) return ALS_E_INVAL;
+    if (dt != ALS_F32 && dt != ALS_F64) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_axpy(n, x, p, alpha, dt, (hipStream_t)stream);
+}
+
+int ncg_axpby(als_ctx *ctx, int64_t n, double a, const void *x, double b, void *y,
+              als_dtype dt, void *stream) {
+    if (!ctx || n < 0 || (n > 0 && (!x || !y)) || !isfinite(a) || !isfinite(b)) return ALS_E_INVAL;
+    if (dt != ALS_F32 && dt != ALS_F64) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_axpby(n, a, x, b, y, dt, (hipStream_t)stream);
+}
+
+int ncg_direction(als_ctx *ctx, int64_t n, const void *x, void *xbar, const void *g_new,
+                  const void *g_old, void *p, double *scal, int restart, int pr_plus,
+                  als_dtype dt, void *stream) {
+    if (!ctx || n < 0 || !scal) return ALS_E_INVAL;
+    if (n > 0 && (!x || !xbar || !g_new || !p || (!restart && !g_old))) return ALS_E_INVAL;
+    if (dt != ALS_F32 && dt != ALS_F64) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_direction(ctx, n, x, xbar, g_new, g_old, p, scal, restart, pr_plus, dt,
+                            (hipStream_t)stream);
+}
+
+int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int ld, double lambda,
+            als_dtype dt, int64_t n_req, const int64_t *req_indptr, const int32_t *req_items,
+            const float *req_vals, void *U_out, int32_t *req_status, void *stream) {
+    if (!ctx || !M || n_items < 0 || ld < n_f || !lambda_ok(lambda) || !dtype_ok(dt, n_f, true) ||
+        n_req < 0 || n_req > INT32_MAX)
+        return ALS_E_INVAL;
+    if (n_req == 0) return ALS_OK;
+    if (!req_indptr || !req_items || !req_vals || !U_out) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_fold_in(ctx, M, n_f, ld, lambda, dt, n_req, req_indptr, req_items, req_vals,
+                          U_out, req_status, (hipStream_t)stream);
+}
+
+}  // extern "C"

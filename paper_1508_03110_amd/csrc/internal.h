@@ -1,0 +1,143 @@
+// Internal declarations shared by the HIP translation units of libalsncg.
+// gfx950 (CDNA4) only: 64-lane wavefronts, MFMA 16x16x4 tiles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "../../include/alsncg.h"
+
+namespace alsncg {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- MFMA tiles
+//
+// v_mfma_{f32,f64}_16x16x4: D[16x16] += A[16x4] B[4x16].  Lane l = 16 g + c
+// (g = l / 16, c = l % 16) supplies A[c][g] and B[g][c]; accumulator
+// register r of lane l holds D[row(g, r)][c], where
+//     f32: row(g, r) = 4 g + r      (each lane group owns 4 consecutive rows)
+//     f64: row(g, r) = g + 4 r      (rows interleaved across lane groups).
+// The contraction index of a Gram update is a free label, so a lane may feed
+// the same register as A and B.  pivot_g / pivot_r invert row().
+template <typename T> struct Mfma;
+
+template <> struct Mfma<float> {
+    typedef float acc4 __attribute__((ext_vector_type(4)));
+    __device__ static inline acc4 mma(float a, float b, acc4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __host__ __device__ static constexpr int row(int g, int r) { return 4 * g + r; }
+    __host__ __device__ static constexpr int pivot_g(int k) { return k >> 2; }
+    __host__ __device__ static constexpr int pivot_r(int k) { return k & 3; }
+};
+
+template <> struct Mfma<double> {
+    typedef double acc4 __attribute__((ext_vector_type(4)));
+    __device__ static inline acc4 mma(double a, double b, acc4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __host__ __device__ static constexpr int row(int g, int r) { return g + 4 * r; }
+    __host__ __device__ static constexpr int pivot_g(int k) { return k & 3; }
+    __host__ __device__ static constexpr int pivot_r(int k) { return k >> 2; }
+};
+
+__device__ inline float readlane(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ inline double readlane(double v, int lane) {
+    long long x = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+    int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 16 lanes that share l / 16 (result in all 16 lanes).
+template <typename T> __device__ inline T sum16(T v) {
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    return v;
+}
+// Sum over the 4 lanes that share l % 16 (result in all 4 lanes).
+template <typename T> __device__ inline T sum4g(T v) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+template <typename T> __device__ inline T sum64(T v) { return sum4g(sum16(v)); }
+
+// ---------------------------------------------------------------- host objects
+
+struct Plan {
+    int64_t n_rows = 0, nnz = 0, n_chunks = 0, n_split_rows = 0, n_slots = 0, chunk = 0,
+            max_row = 0;
+    // device arrays, chunk order = longest first
+    int32_t *chunk_row = nullptr;
+    int64_t *chunk_begin = nullptr;
+    int32_t *chunk_len = nullptr;
+    int32_t *chunk_slot = nullptr;  // -1: the chunk is the whole row
+    // split rows (more than one chunk): slots slot0 .. slot0 + nslot - 1
+    int32_t *split_row = nullptr;
+    int32_t *split_slot0 = nullptr;
+    int32_t *split_nslot = nullptr;
+};
+
+struct Ctx {
+    int device = 0;
+    int num_cu = 256;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    // Returns workspace of at least `bytes` (grows; synchronises before freeing).
+    void *workspace(size_t bytes, hipStream_t stream, int *err);
+};
+
+}  // namespace alsncg
+
+struct als_ctx : alsncg::Ctx {};
+struct als_plan : alsncg::Plan {};
+
+namespace alsncg {
+
+// Kernel launchers (sweep.hip, passes.hip, vec.hip).  Return an als_status.
+int launch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f,
+                 int ld, double lambda, als_dtype dt, const void *X_at, void *grad_out,
+                 int64_t *bad_row, hipStream_t s);
+int launch_fold_in(Ctx *ctx, const void *M, int n_f, int ld, double lambda, als_dtype dt,
+                   int64_t n_req, const int64_t *indptr, const int32_t *items, const float *vals,
+                   void *U_out, int32_t *status, hipStream_t s);
+int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
+                    const void *U, const void *M, int n_f, int ld, double lambda, als_dtype dt,
+                    void *gU, void *gM, double *out2, hipStream_t s);
+int launch_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const void *U,
+                  const void *M, const void *pU, const void *pM, int n_f, int ld, double lambda,
+                  als_dtype dt, double *coeffs, hipStream_t s);
+int launch_backtrack(const double *coeffs, double alpha0, double tau, double c, int max_trials,
+                     double *alpha_out, int32_t *trials_out, hipStream_t s);
+int launch_axpy(int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,
+                hipStream_t s);
+int launch_axpby(int64_t n, double a, const void *x, double b, void *y, als_dtype dt,
+                 hipStream_t s);
+int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void *g_new,
+                     const void *g_old, void *p, double *scal, int restart, int pr_plus,
+                     als_dtype dt, hipStream_t s);
+
+// Deterministic FP64 column sums of a row-major [rows, cols] array (one
+// workgroup, fixed order).  out[k] = sum_r parts[r * cols + k] (+ out[k] when
+// accumulate != 0).
+void launch_sum_columns(const double *parts, int64_t rows, int cols, double *out, int accumulate,
+                        hipStream_t s);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace alsncg
+
+#define ALS_HIP_CHECK(expr)                                   \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return ALS_E_HIP;               \
+    } while (0)

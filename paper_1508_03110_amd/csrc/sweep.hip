@@ -1,0 +1,465 @@
+// ALS half-sweep and fold-in kernels (Eq. (3)/(4) of the paper, Section III-A;
+// Cholesky solve as in Section V-B).
+//
+// One wavefront owns one chunk of one row.  For every group of 4 ratings the
+// wave gathers the 4 fixed-side factor rows straight into registers, one
+// column per lane, and issues one MFMA per upper-triangular 16x16 tile of the
+// Gram matrix.  The gathered row is AUGMENTED with the rating value in column
+// n_f, so the same tiles also accumulate v_i = sum r_ij y_j (column n_f) and
+// sum r_ij^2; factorising the augmented matrix performs the forward
+// substitution R^T z = v for free (z ends up in column n_f of the factor).
+//
+// Register layout of an accumulator tile (a, b) (rows of block a, columns of
+// block b, a <= b): lane l = 16 g + c holds element (16 a + row(g, r),
+// 16 b + c) in register r (row() of the MFMA traits: 4 g + r for FP32,
+// g + 4 r for FP64).  The blocked right-looking Cholesky A = R^T R
+// works on that layout directly:
+//   * the 16 pivots of block row kb are processed on the VALU, one row of R
+//     at a time, the pivot row being broadcast through LDS;
+//   * the trailing update A(a, b) -= R(kb, a)^T R(kb, b) is 4 MFMAs per tile,
+//     again feeding accumulator registers as MFMA operands (the sum over the
+//     16 rows of block kb is order-free).
+// Rows longer than the plan's chunk size are split: each chunk stores its
+// partial Gram tiles, and a second kernel sums them in chunk order (fixed,
+// so results do not depend on scheduling) before the solve.
+#include <math.h>
+
+#include <climits>
+
+#include "internal.h"
+
+namespace alsncg {
+namespace {
+
+template <int NB> struct Tri {
+    static constexpr int NT = NB * (NB + 1) / 2;
+    __host__ __device__ static constexpr int id(int a, int b) { return a * NB - a * (a - 1) / 2 + (b - a); }
+};
+
+template <typename T, int NB> struct Shared {
+    static constexpr int NP = NB * 16;
+    static constexpr int size = 3 * NP + 16 + 16 * 20;
+};
+
+// Gathered operand of one group of 4 ratings: lane (g, c) holds column
+// 16 cb + c of the factor row of rating t + g (the rating itself in column n_f).
+template <typename T, int NB>
+__device__ __forceinline__ void gather_row(T (&gv)[NB], const T *__restrict__ Y, int j, bool ok,
+                                           T r, int ld, int n_f, int c) {
+    const T *row = Y + (int64_t)j * ld;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+        const int col = cb * 16 + c;
+        T v = T(0);
+        if (ok && col < n_f) v = row[col];
+        gv[cb] = (col == n_f) ? r : v;
+    }
+}
+
+// Gram accumulation over ratings [b, e) of one row, software-pipelined:
+// rating ids two groups ahead, factor rows one group ahead of the MFMAs.
+template <typename T, int NB>
+__device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
+                                                const int32_t *__restrict__ idx,
+                                                const float *__restrict__ val, int64_t b, int64_t e,
+                                                const T *__restrict__ Y, int ld, int n_f, int g,
+                                                int c) {
+    if (b >= e) return;
+    T cur[NB];
+    {
+        const int64_t p = b + g;
+        const bool ok = p < e;
+        gather_row<T, NB>(cur, Y, ok ? idx[p] : 0, ok, ok ? (T)val[p] : T(0), ld, n_f, c);
+    }
+    int64_t p1 = b + 4 + g;
+    bool ok1 = p1 < e;
+    int j1 = ok1 ? idx[p1] : 0;
+    T r1 = ok1 ? (T)val[p1] : T(0);
+    for (int64_t t = b; t < e; t += 4) {
+        T nxt[NB];
+        gather_row<T, NB>(nxt, Y, j1, ok1, r1, ld, n_f, c);
+        const int64_t p2 = t + 8 + g;
+        ok1 = p2 < e;
+        j1 = ok1 ? idx[p2] : 0;
+        r1 = ok1 ? (T)val[p2] : T(0);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb)
+                A[Tri<NB>::id(a, bb)] = Mfma<T>::mma(cur[a], cur[bb], A[Tri<NB>::id(a, bb)]);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) cur[cb] = nxt[cb];
+    }
+}
+
+// Regularise, optionally form the gradient 2 (A x_in - v), factorise, solve
+// and store one row.  `sm` is Shared<T, NB>::size elements of LDS.
+template <typename T, int NB>
+__device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT], int64_t row,
+                                           int64_t n_i, T *__restrict__ X, int n_f, int ld,
+                                           T lambda, const T *__restrict__ X_at,
+                                           T *__restrict__ grad_out,
+                                           int64_t *__restrict__ bad_row,
+                                           int32_t *__restrict__ status, int empty_status, T *sm) {
+    typedef Tri<NB> TR;
+    typedef Mfma<T> MF;
+    constexpr int NP = NB * 16;
+    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    T *xs = sm;
+    T *ys = sm + NP;
+    T *w = sm + 2 * NP;
+    T *zs = sm + 3 * NP;
+    T *Rs = zs + 16;
+    T *xrow = X + row * (int64_t)ld;
+
+    if (n_i == 0) {
+        for (int k = lane; k < n_f; k += kWave) {
+            xrow[k] = T(0);
+            if (grad_out) grad_out[row * (int64_t)ld + k] = T(0);
+        }
+        if (status && lane == 0) status[row] = empty_status;
+        return;
+    }
+    const T reg = lambda * (T)n_i;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (MF::row(g, r) == c && 16 * a + c < n_f) A[TR::id(a, a)][r] += reg;
+
+    const int caug = n_f - 16 * (NB - 1);  // lane column of the augmented column
+
+    if (grad_out) {
+        // y = A x_in (A symmetric, upper tiles only), then g = 2 (y - v).
+        const T *xin = X_at ? X_at + row * (int64_t)ld : xrow;
+        for (int k = lane; k < NP; k += kWave) xs[k] = (k < n_f) ? xin[k] : T(0);
+        __syncthreads();
+        T racc[NB][4];
+        T cacc[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            cacc[a] = T(0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) racc[a][r] = T(0);
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb) {
+                const T xv = xs[16 * bb + c];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    racc[a][r] += A[TR::id(a, bb)][r] * xv;
+                    if (a < bb) cacc[bb] += A[TR::id(a, bb)][r] * xs[16 * a + MF::row(g, r)];
+                }
+            }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            cacc[a] = sum4g(cacc[a]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) racc[a][r] = sum16(racc[a][r]);
+        }
+        if (c == 0) {
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ys[16 * a + MF::row(g, r)] = racc[a][r];
+        }
+        if (c == caug) {
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w[16 * a + MF::row(g, r)] = A[TR::id(a, NB - 1)][r];
+        }
+        __syncthreads();
+        if (g == 0) {
+#pragma unroll
+            for (int a = 0; a < NB; ++a) ys[16 * a + c] += cacc[a];
+        }
+        __syncthreads();
+        for (int k = lane; k < n_f; k += kWave)
+            grad_out[row * (int64_t)ld + k] = T(2) * (ys[k] - w[k]);
+        __syncthreads();
+    }
+
+    // ---- blocked Cholesky of the augmented matrix (pivots 0 .. n_f-1 only)
+    bool bad = false;
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = 16 * kb + kk;
+            if (k < n_f) {
+                const int gk = MF::pivot_g(kk), rk = MF::pivot_r(kk);
+                T akk = readlane(A[TR::id(kb, kb)][rk], 16 * gk + kk);
+                if (!(akk > T(0))) {
+                    bad = true;
+                    akk = T(1);
+                }
+                const T inv = T(1) / sqrt(akk);
+#pragma unroll
+                for (int b = kb; b < NB; ++b) {
+                    if (g == gk) {
+                        const T v = A[TR::id(kb, b)][rk] * inv;
+                        A[TR::id(kb, b)][rk] = v;
+                        w[16 * b + c] = (16 * b + c > k) ? v : T(0);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int b = kb; b < NB; ++b) {
+                    const T cv = w[16 * b + c];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) A[TR::id(kb, b)][r] -= w[16 * kb + MF::row(g, r)] * cv;
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int a = kb + 1; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    A[TR::id(a, bb)] =
+                        Mfma<T>::mma(-A[TR::id(kb, a)][s], A[TR::id(kb, bb)][s], A[TR::id(a, bb)]);
+    }
+
+    // ---- back substitution R x = z, z = column n_f of the factor
+    if (c == caug) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ys[16 * a + MF::row(g, r)] = A[TR::id(a, NB - 1)][r];
+    }
+    for (int k = lane; k < NP; k += kWave) xs[k] = T(0);
+    __syncthreads();
+    T myx = T(0);
+#pragma unroll
+    for (int kb = NB - 1; kb >= 0; --kb) {
+        if (16 * kb < n_f) {
+            T part[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int bb = kb + 1; bb < NB; ++bb) {
+                const T xv = xs[16 * bb + c];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) part[r] += A[TR::id(kb, bb)][r] * xv;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                part[r] = sum16(part[r]);
+                Rs[MF::row(g, r) * 20 + c] = A[TR::id(kb, kb)][r];
+            }
+            if (c == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) zs[MF::row(g, r)] = ys[16 * kb + MF::row(g, r)] - part[r];
+            }
+            __syncthreads();
+            T Ri[16];
+            T zi = T(0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) Ri[q] = Rs[(lane & 15) * 20 + q];  // lanes >= 16: unused copies
+            zi = zs[lane & 15];
+#pragma unroll
+            for (int kk = 15; kk >= 0; --kk) {
+                if (16 * kb + kk < n_f) {
+                    const T zk = readlane(zi, kk);
+                    const T dk = readlane(Ri[kk], kk);
+                    const T xk = zk / dk;
+                    if (lane == kk) myx = xk;
+                    zi -= Ri[kk] * xk;
+                }
+            }
+            if (lane < 16 && 16 * kb + lane < n_f) xs[16 * kb + lane] = myx;
+            __syncthreads();
+        }
+    }
+    for (int k = lane; k < n_f; k += kWave) xrow[k] = bad ? T(NAN) : xs[k];
+    if (lane == 0) {
+        if (bad && bad_row) atomicMin((unsigned long long *)bad_row, (unsigned long long)row);
+        if (status) status[row] = bad ? (int32_t)ALS_E_NOT_SPD : 0;
+    }
+}
+
+// One chunk per 64-lane workgroup.  chunk_row == nullptr: chunk q is row q
+// in full (fold-in and unplanned use).
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void sweep_chunks_kernel(
+    const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
+    const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
+    T lambda, int64_t n_chunks, const int32_t *__restrict__ chunk_row,
+    const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
+    const int32_t *__restrict__ chunk_slot, typename Mfma<T>::acc4 *__restrict__ partial,
+    const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row,
+    int32_t *__restrict__ status, int empty_status) {
+    typedef typename Mfma<T>::acc4 acc4;
+    typedef Tri<NB> TR;
+    __shared__ T sm[Shared<T, NB>::size];
+    const int64_t q = blockIdx.x;
+    if (q >= n_chunks) return;
+    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    int64_t row, b, len;
+    int slot;
+    if (chunk_row) {
+        row = chunk_row[q];
+        b = chunk_begin[q];
+        len = chunk_len[q];
+        slot = chunk_slot[q];
+    } else {
+        row = q;
+        b = indptr[q];
+        len = indptr[q + 1] - b;
+        slot = -1;
+    }
+    acc4 A[TR::NT];
+#pragma unroll
+    for (int t = 0; t < TR::NT; ++t) A[t] = acc4{T(0), T(0), T(0), T(0)};
+    gram_accumulate<T, NB>(A, idx, val, b, b + len, Y, ld, n_f, g, c);
+    if (slot >= 0) {
+        acc4 *dst = partial + (int64_t)slot * TR::NT * kWave;
+#pragma unroll
+        for (int t = 0; t < TR::NT; ++t) dst[t * kWave + lane] = A[t];
+        return;
+    }
+    const int64_t n_i = indptr[row + 1] - indptr[row];
+    finish_row<T, NB>(A, row, n_i, X, n_f, ld, lambda, X_at, grad_out, bad_row, status,
+                      empty_status, sm);
+}
+
+// Second stage for rows split over several chunks: fixed-order sum of the
+// partial Gram tiles, then the row solve.
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void sweep_split_kernel(
+    const int64_t *__restrict__ indptr, T *__restrict__ X, int n_f, int ld, T lambda,
+    int64_t n_split, const int32_t *__restrict__ split_row, const int32_t *__restrict__ split_slot0,
+    const int32_t *__restrict__ split_nslot, const typename Mfma<T>::acc4 *__restrict__ partial,
+    const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row) {
+    typedef typename Mfma<T>::acc4 acc4;
+    typedef Tri<NB> TR;
+    __shared__ T sm[Shared<T, NB>::size];
+    const int64_t s = blockIdx.x;
+    if (s >= n_split) return;
+    const int lane = threadIdx.x;
+    const int64_t row = split_row[s];
+    const int64_t s0 = split_slot0[s];
+    const int ns = split_nslot[s];
+    acc4 A[TR::NT];
+#pragma unroll
+    for (int t = 0; t < TR::NT; ++t) A[t] = acc4{T(0), T(0), T(0), T(0)};
+    for (int u = 0; u < ns; ++u) {
+        const acc4 *src = partial + (s0 + u) * TR::NT * kWave;
+#pragma unroll
+        for (int t = 0; t < TR::NT; ++t) A[t] += src[t * kWave + lane];
+    }
+    const int64_t n_i = indptr[row + 1] - indptr[row];
+    finish_row<T, NB>(A, row, n_i, X, n_f, ld, lambda, X_at, grad_out, bad_row, nullptr, 0, sm);
+}
+
+__global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
+
+template <typename T, int NB>
+int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
+              T lambda, const T *X_at, T *grad_out, int64_t *bad_row, int32_t *status, int empty_status,
+              int64_t n_rows_unplanned, hipStream_t s) {
+    typedef typename Mfma<T>::acc4 acc4;
+    typedef Tri<NB> TR;
+    if (bad_row) hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, bad_row, (int64_t)LLONG_MAX);
+    if (!plan) {
+        if (n_rows_unplanned > 0)
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB>), dim3((unsigned)n_rows_unplanned),
+                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
+                               lambda, n_rows_unplanned, nullptr, nullptr, nullptr, nullptr,
+                               (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status);
+        return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+    }
+    acc4 *partial = nullptr;
+    if (plan->n_slots > 0) {
+        int err = ALS_OK;
+        partial = (acc4 *)ctx->workspace((size_t)plan->n_slots * TR::NT * kWave * sizeof(acc4), s, &err);
+        if (!partial) return err;
+    }
+    if (plan->n_chunks > 0)
+        hipLaunchKernelGGL((sweep_chunks_kernel<T, NB>), dim3((unsigned)plan->n_chunks), dim3(kWave),
+                           0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld, lambda,
+                           plan->n_chunks, plan->chunk_row, plan->chunk_begin, plan->chunk_len,
+                           plan->chunk_slot, partial, X_at, grad_out, bad_row, status,
+                           empty_status);
+    if (plan->n_split_rows > 0)
+        hipLaunchKernelGGL((sweep_split_kernel<T, NB>), dim3((unsigned)plan->n_split_rows),
+                           dim3(kWave), 0, s, R->indptr, X, n_f, ld, lambda, plan->n_split_rows,
+                           plan->split_row, plan->split_slot0, plan->split_nslot, partial, X_at,
+                           grad_out, bad_row);
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
+template <typename T>
+int dispatch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f,
+                   int ld, double lambda, const void *X_at, void *grad_out, int64_t *bad_row, int32_t *status,
+                   int empty_status, int64_t n_rows_unplanned, hipStream_t s) {
+    const int nb = (n_f + 1 + 15) / 16;
+#define ALS_SWEEP_CASE(NBV)                                                                      \
+    case NBV:                                                                                    \
+        return run_sweep<T, NBV>(ctx, plan, R, (const T *)Y, (T *)X, n_f, ld, (T)lambda,         \
+                                 (const T *)X_at, (T *)grad_out, bad_row, status, empty_status, n_rows_unplanned, \
+                                 s);
+    if constexpr (sizeof(T) == 4) {
+        switch (nb) {
+            ALS_SWEEP_CASE(1)
+            ALS_SWEEP_CASE(2)
+            ALS_SWEEP_CASE(3)
+            ALS_SWEEP_CASE(4)
+            ALS_SWEEP_CASE(5)
+            ALS_SWEEP_CASE(6)
+            ALS_SWEEP_CASE(7)
+            ALS_SWEEP_CASE(8)
+            ALS_SWEEP_CASE(9)
+            default: return ALS_E_INVAL;
+        }
+    } else {
+        switch (nb) {
+            ALS_SWEEP_CASE(1)
+            ALS_SWEEP_CASE(2)
+            ALS_SWEEP_CASE(3)
+            ALS_SWEEP_CASE(4)
+            ALS_SWEEP_CASE(5)
+            ALS_SWEEP_CASE(6)
+            default: return ALS_E_INVAL;
+        }
+    }
+#undef ALS_SWEEP_CASE
+}
+
+}  // namespace
+
+int launch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f,
+                 int ld, double lambda, als_dtype dt, const void *X_at, void *grad_out,
+                 int64_t *bad_row, hipStream_t s) {
+    if (dt == ALS_F32)
+        return dispatch_sweep<float>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out, bad_row,
+                                     nullptr, 0, 0, s);
+    if (dt == ALS_F64)
+        return dispatch_sweep<double>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out,
+                                      bad_row, nullptr, 0, 0, s);
+    return ALS_E_INVAL;
+}
+
+int launch_fold_in(Ctx *ctx, const void *M, int n_f, int ld, double lambda, als_dtype dt,
+                   int64_t n_req, const int64_t *indptr, const int32_t *items, const float *vals,
+                   void *U_out, int32_t *status, hipStream_t s) {
+    als_csr R;
+    R.n_rows = n_req;
+    R.n_cols = 0;
+    R.nnz = 0;
+    R.indptr = indptr;
+    R.indices = items;
+    R.values = vals;
+    if (dt == ALS_F32)
+        return dispatch_sweep<float>(ctx, nullptr, &R, M, U_out, n_f, ld, lambda, nullptr, nullptr,
+                                     nullptr, status, ALS_E_INVAL, n_req, s);
+    if (dt == ALS_F64)
+        return dispatch_sweep<double>(ctx, nullptr, &R, M, U_out, n_f, ld, lambda, nullptr,
+                                      nullptr, nullptr, status, ALS_E_INVAL, n_req, s);
+    return ALS_E_INVAL;
+}
+
+}  // namespace alsncg

@@ -1,0 +1,233 @@
+// NCG vector layer of Algorithm 2 on the flat unknown x of Eq. (5): the step
+// x + alpha p, the preconditioned direction with beta of Eq. (8), the
+// backtracking line search of Algorithm 4 on the quartic coefficients, and
+// the fixed-order FP64 reductions everything else uses.  These are streaming
+// (HBM-bound) kernels: grid-stride loops over the vectors, FP64 dots reduced
+// per block into one partial each, partials summed by one workgroup in a
+// fixed order.
+#include <math.h>
+
+#include "internal.h"
+
+namespace alsncg {
+namespace {
+
+constexpr int kVecThreads = 256;
+constexpr int kVecBlocks = 2048;  // fixed: the reduction order must not depend on n
+
+// ---------------------------------------------------------------- reductions
+
+__global__ __launch_bounds__(1024) void sum_columns_kernel(const double *__restrict__ parts,
+                                                           int64_t rows, int cols,
+                                                           double *__restrict__ out,
+                                                           int accumulate) {
+    __shared__ double red[1024];
+    for (int k = 0; k < cols; ++k) {
+        double s = 0.0;
+        for (int64_t r = threadIdx.x; r < rows; r += 1024) s += parts[r * cols + k];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = accumulate ? out[k] + red[0] : red[0];
+        __syncthreads();
+    }
+}
+
+template <int NV>
+__device__ inline void block_sum_store(double (&v)[NV], double *dst) {
+    __shared__ double red[NV][kVecThreads / kWave];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        v[k] = sum64(v[k]);
+        if (lane == 0) red[k][wv] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < kVecThreads / kWave; ++w) s += red[k][w];
+            dst[k] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- axpy
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void axpy_kernel(int64_t n, T *__restrict__ x,
+                                                           const T *__restrict__ p,
+                                                           const double *__restrict__ alpha) {
+    const double a = *alpha;
+    for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kVecThreads)
+        x[i] = (T)((double)x[i] + a * (double)p[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void axpby_kernel(int64_t n, double a,
+                                                            const T *__restrict__ x, double b,
+                                                            T *__restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kVecThreads) {
+        const double yv = b != 0.0 ? b * (double)y[i] : 0.0;
+        y[i] = (T)(a * (double)x[i] + yv);
+    }
+}
+
+// ---------------------------------------------------------------- direction
+
+// gbar = x - xbar (stored over xbar); partial sums of
+//   [gbar.(g_new - g_old), gbar.g_new, g_new.g_new].
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void direction_dots_kernel(
+    int64_t n, const T *__restrict__ x, T *__restrict__ xbar, const T *__restrict__ gn,
+    const T *__restrict__ go, double *__restrict__ part) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kVecThreads) {
+        const T gb = x[i] - xbar[i];
+        xbar[i] = gb;
+        const double g1 = (double)gn[i];
+        const double g0 = go ? (double)go[i] : 0.0;
+        v[0] += (double)gb * (g1 - g0);
+        v[1] += (double)gb * g1;
+        v[2] += g1 * g1;
+    }
+    block_sum_store<3>(v, part + 3 * (int64_t)blockIdx.x);
+}
+
+// scal[0] = den (in: gbar_k.g_k, out: gbar_{k+1}.g_{k+1}); scal[1] = beta;
+// scal[2] = ||g||^2; scal[3] = numerator of Eq. (8).
+__global__ void direction_beta_kernel(const double *__restrict__ sums, double *__restrict__ scal,
+                                      int restart, int pr_plus) {
+    const double num = sums[0], den_new = sums[1], gg = sums[2];
+    const double den = scal[0];
+    double beta = 0.0;
+    if (!restart && den != 0.0 && isfinite(den)) beta = num / den;
+    if (!isfinite(beta)) beta = 0.0;
+    if (pr_plus && beta < 0.0) beta = 0.0;
+    scal[0] = den_new;
+    scal[1] = beta;
+    scal[2] = gg;
+    scal[3] = num;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void direction_update_kernel(
+    int64_t n, const T *__restrict__ gbar, T *__restrict__ p, const double *__restrict__ scal) {
+    const double beta = scal[1];
+    for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kVecThreads)
+        p[i] = (T)(beta * (double)p[i] - (double)gbar[i]);
+}
+
+// ---------------------------------------------------------------- backtracking
+
+__global__ void backtrack_kernel(const double *__restrict__ C, double alpha0, double tau, double c,
+                                 int max_trials, double *__restrict__ alpha_out,
+                                 int32_t *__restrict__ trials_out) {
+    // no FMA contraction: the accept/reject decision must be taken with the
+    // same roundings as a plain evaluation of the test
+#pragma clang fp contract(off)
+    const double c1 = C[1], c2 = C[2], c3 = C[3], c4 = C[4];
+    double alpha = alpha0, acc = 0.0;
+    int n = -1;
+    if (c1 < 0.0) {
+        for (int t = 0; t < max_trials; ++t) {
+            const double test = (1.0 - c) * c1 + alpha * (c2 + alpha * (c3 + alpha * c4));
+            if (test <= 0.0) {
+                n = t;
+                acc = alpha;
+                break;
+            }
+            alpha = tau * alpha;
+        }
+    }
+    *alpha_out = acc;
+    if (trials_out) *trials_out = n;
+}
+
+}  // namespace
+
+void launch_sum_columns(const double *parts, int64_t rows, int cols, double *out, int accumulate,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(sum_columns_kernel, dim3(1), dim3(1024), 0, s, parts, rows, cols, out,
+                       accumulate);
+}
+
+int launch_backtrack(const double *coeffs, double alpha0, double tau, double c, int max_trials,
+                     double *alpha_out, int32_t *trials_out, hipStream_t s) {
+    hipLaunchKernelGGL(backtrack_kernel, dim3(1), dim3(1), 0, s, coeffs, alpha0, tau, c,
+                       max_trials, alpha_out, trials_out);
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
+static unsigned vec_grid(int64_t n) {
+    const int64_t b = (n + kVecThreads - 1) / kVecThreads;
+    return (unsigned)(b < 1 ? 1 : (b > kVecBlocks ? kVecBlocks : b));
+}
+
+int launch_axpy(int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,
+                hipStream_t s) {
+    if (n == 0) return ALS_OK;
+    if (dt == ALS_F32)
+        hipLaunchKernelGGL(axpy_kernel<float>, dim3(vec_grid(n)), dim3(kVecThreads), 0, s, n,
+                           (float *)x, (const float *)p, alpha);
+    else if (dt == ALS_F64)
+        hipLaunchKernelGGL(axpy_kernel<double>, dim3(vec_grid(n)), dim3(kVecThreads), 0, s, n,
+                           (double *)x, (const double *)p, alpha);
+    else
+        return ALS_E_INVAL;
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
+int launch_axpby(int64_t n, double a, const void *x, double b, void *y, als_dtype dt,
+                 hipStream_t s) {
+    if (n == 0) return ALS_OK;
+    if (dt == ALS_F32)
+        hipLaunchKernelGGL(axpby_kernel<float>, dim3(vec_grid(n)), dim3(kVecThreads), 0, s, n, a,
+                           (const float *)x, b, (float *)y);
+    else if (dt == ALS_F64)
+        hipLaunchKernelGGL(axpby_kernel<double>, dim3(vec_grid(n)), dim3(kVecThreads), 0, s, n, a,
+                           (const double *)x, b, (double *)y);
+    else
+        return ALS_E_INVAL;
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
+int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void *g_new,
+                     const void *g_old, void *p, double *scal, int restart, int pr_plus,
+                     als_dtype dt, hipStream_t s) {
+    int err = ALS_OK;
+    double *part = (double *)ctx->workspace((size_t)(kVecBlocks * 3 + 8) * sizeof(double), s, &err);
+    if (!part) return err;
+    double *sums = part + kVecBlocks * 3;
+    // fixed grid so the reduction order is the same for every n
+    const unsigned grid = kVecBlocks;
+    if (dt == ALS_F32)
+        hipLaunchKernelGGL(direction_dots_kernel<float>, dim3(grid), dim3(kVecThreads), 0, s, n,
+                           (const float *)x, (float *)xbar, (const float *)g_new,
+                           restart ? nullptr : (const float *)g_old, part);
+    else if (dt == ALS_F64)
+        hipLaunchKernelGGL(direction_dots_kernel<double>, dim3(grid), dim3(kVecThreads), 0, s, n,
+                           (const double *)x, (double *)xbar, (const double *)g_new,
+                           restart ? nullptr : (const double *)g_old, part);
+    else
+        return ALS_E_INVAL;
+    launch_sum_columns(part, kVecBlocks, 3, sums, 0, s);
+    hipLaunchKernelGGL(direction_beta_kernel, dim3(1), dim3(1), 0, s, sums, scal, restart, pr_plus);
+    if (dt == ALS_F32)
+        hipLaunchKernelGGL(direction_update_kernel<float>, dim3(vec_grid(n)), dim3(kVecThreads), 0,
+                           s, n, (const float *)xbar, (float *)p, scal);
+    else
+        hipLaunchKernelGGL(direction_update_kernel<double>, dim3(vec_grid(n)), dim3(kVecThreads), 0,
+                           s, n, (const double *)xbar, (double *)p, scal);
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
+}  // namespace alsncg

@@ -1,0 +1,303 @@
+"""ALS (Algorithm 1) and ALS-NCG (Algorithm 2) driven through libalsncg.
+
+Device memory comes from PyTorch; every arithmetic step runs in the HIP
+library through the C ABI (``_lib``).  The host only sequences the calls
+and, once per ALS-NCG iteration, reads back 16 scalars (the quartic
+coefficients, the step, beta, norms) to take the line-search decisions.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+TAU, C_ARMIJO, ALPHA0, MAX_TRIALS = 0.9, 0.5, 10.0, 400  # Section V-C
+
+# layout of the per-solver FP64 scalar block on the device
+S_DEN, S_BETA, S_GG, S_NUM = 0, 1, 2, 3
+S_COEF = 4          # 4..8: C0..C4
+S_ALPHA = 9
+S_F, S_GN = 10, 11  # ncg_gradient out2
+
+
+class Context:
+    """Owns an als_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the ALS-NCG library needs an MI355X (gfx950)")
+        self.device = int(device)
+        self.handle = L.als_ctx_create(self.device)
+        self.torch_device = torch.device("cuda", self.device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.als_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        return L.als_ctx_workspace_bytes(self.handle)
+
+
+class DeviceCsr:
+    """One orientation of R resident in HBM, with its row plan."""
+
+    def __init__(self, ctx: Context, indptr, indices, values, n_cols: int, chunk: int = 0):
+        dev = ctx.torch_device
+        self.indptr = torch.as_tensor(np.ascontiguousarray(indptr, dtype=np.int64)).to(dev)
+        self.indices = torch.as_tensor(np.ascontiguousarray(indices, dtype=np.int32)).to(dev)
+        self.values = torch.as_tensor(np.ascontiguousarray(values, dtype=np.float32)).to(dev)
+        self.n_rows = int(self.indptr.numel() - 1)
+        self.n_cols = int(n_cols)
+        self.nnz = int(self.indices.numel())
+        self.csr = L.Csr(self.n_rows, self.n_cols, self.nnz, self.indptr.data_ptr(),
+                         self.indices.data_ptr() if self.nnz else 0,
+                         self.values.data_ptr() if self.nnz else 0)
+        self.ctx = ctx
+        self.plan = L.als_plan_create(ctx.handle, self.csr, int(chunk))
+
+    @classmethod
+    def from_host(cls, ctx, A, chunk: int = 0):
+        """A: any object with n_rows, n_cols, indptr, indices, values (host arrays)."""
+        return cls(ctx, A.indptr, A.indices, A.values, A.n_cols, chunk)
+
+    def info(self) -> dict:
+        return L.als_plan_info(self.plan)
+
+    def close(self):
+        if getattr(self, "plan", None):
+            L.als_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceProblem:
+    """R (users x items) and R^T on the device plus n_f, lambda and the factor type."""
+
+    def __init__(self, ctx: Context, R, Rt, n_f: int, lam: float, dtype=torch.float32,
+                 chunk: int = 0, chunk_t: Optional[int] = None, ld: Optional[int] = None):
+        self.ctx = ctx
+        self.R = R if isinstance(R, DeviceCsr) else DeviceCsr.from_host(ctx, R, chunk)
+        self.Rt = Rt if isinstance(Rt, DeviceCsr) else DeviceCsr.from_host(
+            ctx, Rt, chunk if chunk_t is None else chunk_t)
+        if self.R.n_rows != self.Rt.n_cols or self.R.n_cols != self.Rt.n_rows or self.R.nnz != self.Rt.nnz:
+            raise ValueError("R and R^T shapes disagree")
+        self.n_u, self.n_m = self.R.n_rows, self.R.n_cols
+        self.n_f, self.lam = int(n_f), float(lam)
+        self.ld = int(ld or n_f)
+        self.dtype = dtype
+        self.dt = L.dtype_code(dtype)
+        self.N = (self.n_u + self.n_m) * self.ld
+
+    # -- helpers over a flat [U; M] buffer
+    def zeros(self, n=None):
+        return torch.zeros(self.N if n is None else n, dtype=self.dtype, device=self.ctx.torch_device)
+
+    def U(self, x):
+        return x[: self.n_u * self.ld].view(self.n_u, self.ld)
+
+    def M(self, x):
+        return x[self.n_u * self.ld:].view(self.n_m, self.ld)
+
+    def pack(self, U, M):
+        x = self.zeros()
+        self.U(x)[:, : self.n_f] = torch.as_tensor(np.asarray(U), dtype=self.dtype).to(x.device)
+        self.M(x)[:, : self.n_f] = torch.as_tensor(np.asarray(M), dtype=self.dtype).to(x.device)
+        return x
+
+    # -- single ABI calls
+    def sweep(self, side: str, Y, X, X_at=None, grad_out=None, bad_row=None):
+        A = self.R if side == "U" else self.Rt
+        L.als_sweep(self.ctx.handle, A.plan, A.csr, Y, X, self.n_f, self.ld, self.lam, self.dt,
+                    X_at, grad_out, bad_row)
+
+    def gradient(self, U, M, gU=None, gM=None, out2=None):
+        L.ncg_gradient(self.ctx.handle, self.R.plan, self.R.csr, self.Rt.plan, self.Rt.csr, U, M,
+                       self.n_f, self.ld, self.lam, self.dt, gU, gM, out2)
+
+    def coeffs(self, U, M, pU, pM, out):
+        L.linesearch_coeffs(self.ctx.handle, self.R.plan, self.R.csr, self.Rt.csr, U, M, pU, pM,
+                            self.n_f, self.ld, self.lam, self.dt, out)
+
+    def loss_and_gnorm(self, x, g=None):
+        """(f(x), ||grad f(x)||) by one gradient pass per orientation (FP64 reductions)."""
+        out = torch.zeros(2, dtype=torch.float64, device=self.ctx.torch_device)
+        g = self.zeros() if g is None else g
+        self.gradient(self.U(x), self.M(x), self.U(g), self.M(g), out)
+        f, gg = out.cpu().tolist()
+        return f, math.sqrt(max(gg, 0.0))
+
+
+class Als:
+    """Algorithm 1: U half-sweep from M, then M half-sweep from the new U."""
+
+    def __init__(self, prob: DeviceProblem, x0=None):
+        self.p = prob
+        self.x = prob.zeros() if x0 is None else x0
+        self.k = 0
+
+    def sweep(self):
+        P = self.p
+        P.sweep("U", P.M(self.x), P.U(self.x))
+        P.sweep("M", P.U(self.x), P.M(self.x))
+        self.k += 1
+
+
+class AlsNcg:
+    """Algorithm 2 (ALS-NCG) with the preconditioned beta of Eq. (8) and the
+    one-pass quartic backtracking line search of Section V-C.
+
+    Safeguards (the paper is silent on failures): a direction with
+    g^T p >= 0 is reset to -gbar; if the line search still fails, the ALS
+    point P(x_k) is taken and the next direction restarts (beta = 0).
+    """
+
+    def __init__(self, prob: DeviceProblem, safeguard: bool = True, pr_plus: bool = False,
+                 alpha0: float = ALPHA0, tau: float = TAU, c: float = C_ARMIJO,
+                 max_trials: int = MAX_TRIALS):
+        self.p = prob
+        self.safeguard, self.pr_plus = safeguard, pr_plus
+        self.alpha0, self.tau, self.c, self.max_trials = alpha0, tau, c, max_trials
+        dev = prob.ctx.torch_device
+        self.x = prob.zeros()
+        self.pdir = prob.zeros()
+        self.xbar = prob.zeros()      # P(x); after the direction update it holds gbar
+        self.g_new = prob.zeros()
+        self.g_old = prob.zeros()
+        self.scal = torch.zeros(16, dtype=torch.float64, device=dev)
+        self.trials = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.k = 0
+        self.restarts = self.safeguards = 0
+        self.f = float("nan")
+        self.alpha = float("nan")
+        self.n_trials = 0
+        self.coef = None
+        self.timers = None  # {phase: [(start, end) torch.cuda.Event pairs]} when timing
+
+    def enable_timing(self, on: bool = True):
+        """Record HIP events (on torch's current stream, where the library
+        launches) around every phase of each iteration."""
+        self.timers = {} if on else None
+
+    def _mark(self, name):
+        if self.timers is None:
+            return None
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.timers.setdefault(name, []).append([e, None])
+        return name
+
+    def _done(self, name):
+        if name is not None:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            self.timers[name][-1][1] = e
+
+    def phase_ms(self) -> dict:
+        """Mean milliseconds per launch of each timed phase (synchronises)."""
+        torch.cuda.synchronize()
+        return {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in (self.timers or {}).items()}
+
+    # -- pieces
+    def _precondition_and_gradient(self):
+        """xbar = P(x) (two half-sweeps); g_new = grad f(x): the U block fused
+        into the U half-sweep, the M block by one pass over R^T."""
+        P = self.p
+        t = self._mark("sweep_U")
+        P.sweep("U", P.M(self.x), P.U(self.xbar), X_at=P.U(self.x), grad_out=P.U(self.g_new))
+        self._done(t)
+        t = self._mark("sweep_M")
+        P.sweep("M", P.U(self.xbar), P.M(self.xbar))
+        self._done(t)
+        t = self._mark("gradient_M")
+        P.gradient(P.U(self.x), P.M(self.x), None, P.M(self.g_new), None)
+        self._done(t)
+
+    def _direction(self, restart: bool):
+        P = self.p
+        t = self._mark("direction")
+        L.ncg_direction(P.ctx.handle, P.N, self.x, self.xbar, self.g_new, self.g_old, self.pdir,
+                        self.scal, 1 if restart else 0, 1 if self.pr_plus else 0, P.dt)
+        self._done(t)
+        self.g_new, self.g_old = self.g_old, self.g_new
+
+    def _line_search(self):
+        P = self.p
+        coef = self.scal[S_COEF:S_COEF + 5]
+        t = self._mark("linesearch_coeffs")
+        P.coeffs(P.U(self.x), P.M(self.x), P.U(self.pdir), P.M(self.pdir), coef)
+        self._done(t)
+        L.ncg_backtrack(P.ctx.handle, coef, self.alpha0, self.tau, self.c, self.max_trials,
+                        self.scal[S_ALPHA:S_ALPHA + 1], self.trials)
+        host = self.scal.cpu().numpy()
+        n = int(self.trials.cpu().item())
+        C = host[S_COEF:S_COEF + 5].copy()
+        alpha = float(host[S_ALPHA]) if n >= 0 else None
+        return C, alpha, n
+
+    # -- Algorithm 2
+    def init(self, U0, M0):
+        self.x = self.p.pack(U0, M0)
+        self._precondition_and_gradient()
+        self._direction(restart=True)       # p_0 = -gbar_0
+        self.k = 0
+        return self
+
+    def step(self):
+        P = self.p
+        C, alpha, n = self._line_search()
+        if self.safeguard and (C[1] >= 0.0 or alpha is None):
+            L.ncg_axpby(P.ctx.handle, P.N, -1.0, self.xbar, 0.0, self.pdir, P.dt)  # p = -gbar
+            self.restarts += 1
+            C, alpha, n = self._line_search()
+        restart = False
+        if alpha is None or (self.safeguard and C[1] >= 0.0):
+            if not self.safeguard:
+                raise RuntimeError("line search failed at iteration %d" % self.k)
+            L.ncg_axpby(P.ctx.handle, P.N, -1.0, self.xbar, 1.0, self.x, P.dt)  # x = x - gbar = P(x)
+            self.safeguards += 1
+            restart = True
+            self.f, self.alpha = float("nan"), float("nan")
+        else:
+            L.ncg_axpy(P.ctx.handle, P.N, self.x, self.pdir, self.scal[S_ALPHA:S_ALPHA + 1], P.dt)
+            self.alpha = alpha
+            self.f = float(np.polyval(C[::-1], alpha))
+        self.coef, self.n_trials = C, n
+        self._precondition_and_gradient()
+        self._direction(restart=restart)
+        self.k += 1
+        return self
+
+    def gnorm(self) -> float:
+        """||g(x_k)|| from the last direction update (no extra pass)."""
+        return math.sqrt(max(float(self.scal[S_GG].item()), 0.0))
+
+
+def fold_in(ctx: Context, M, lam: float, req, n_f: int, ld: Optional[int] = None):
+    """Batched fold-in of host request CSR `req` against device factors M
+    [n_items, ld]; returns (U [n_req, ld] device tensor, status int32)."""
+    ld = int(ld or n_f)
+    dev = ctx.torch_device
+    ip = torch.as_tensor(np.ascontiguousarray(req.indptr, dtype=np.int64)).to(dev)
+    it = torch.as_tensor(np.ascontiguousarray(req.indices, dtype=np.int32)).to(dev)
+    va = torch.as_tensor(np.ascontiguousarray(req.values, dtype=np.float32)).to(dev)
+    n_req = ip.numel() - 1
+    U = torch.zeros((n_req, ld), dtype=M.dtype, device=dev)
+    st = torch.zeros(n_req, dtype=torch.int32, device=dev)
+    L.fold_in(ctx.handle, M, M.shape[0], n_f, ld, lam, L.dtype_code(M.dtype), n_req, ip, it, va, U, st)
+    return U, st
