@@ -55,6 +55,21 @@ __device__ inline double readlane(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1/sqrt(d) for d > 0: hardware reciprocal square root refined by Newton
+// steps y <- y (3 - d y^2) / 2 (one for FP32, two for FP64), accurate to a
+// few units in the last place; avoids the long IEEE sqrt and divide sequences
+// on the Cholesky pivots.
+__device__ inline float inv_sqrt(float d) {
+    float y = __builtin_amdgcn_rsqf(d);
+    return y * (1.5f - 0.5f * d * y * y);
+}
+__device__ inline double inv_sqrt(double d) {
+    double y = (double)__builtin_amdgcn_rsqf((float)d);
+    y = y * (1.5 - 0.5 * d * y * y);
+    y = y * (1.5 - 0.5 * d * y * y);
+    return y * (1.5 - 0.5 * d * y * y);
+}
+
 // Sum over the 16 lanes that share l / 16 (result in all 16 lanes).
 template <typename T> __device__ inline T sum16(T v) {
     v += __shfl_xor(v, 1);

@@ -36,9 +36,13 @@ template <int NB> struct Tri {
     __host__ __device__ static constexpr int id(int a, int b) { return a * NB - a * (a - 1) / 2 + (b - a); }
 };
 
+// LDS per wavefront: two vectors of NB*16, one 16x17 transpose tile and the
+// NB inverted diagonal factors R_kk^{-T} (16x17 each, kept for the back
+// substitution).
 template <typename T, int NB> struct Shared {
     static constexpr int NP = NB * 16;
-    static constexpr int size = 3 * NP + 16 + 16 * 20;
+    static constexpr int TS = 16 * 17;
+    static constexpr int size = 2 * NP + TS + NB * TS;
 };
 
 // Gathered operand of one group of 4 ratings: lane (g, c) holds column
@@ -107,9 +111,7 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     T *xs = sm;
     T *ys = sm + NP;
-    T *w = sm + 2 * NP;
-    T *zs = sm + 3 * NP;
-    T *Rs = zs + 16;
+    T *w = sm + 2 * NP;  // v during the gradient (shares space with the factor scratch)
     T *xrow = X + row * (int64_t)ld;
 
     if (n_i == 0) {
@@ -182,37 +184,65 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
         __syncthreads();
     }
 
-    // ---- blocked Cholesky of the augmented matrix (pivots 0 .. n_f-1 only)
+    // ---- blocked Cholesky A = R^T R of the augmented matrix (pivots 0 .. n_f-1)
+    //
+    // Block row kb: the 16x16 diagonal tile is copied to LDS and factored
+    // together with an identity block, 32 columns = 32 lanes, each lane owning
+    // one column in 16 registers; row kk of the pivot block is broadcast with
+    // readlane.  Lanes 0..15 end with the columns of R_kk, lanes 16..31 with
+    // those of R_kk^{-T} (the forward substitution R_kk^T Y = I).  The other
+    // tiles of the block row are then R(kb, b) = R_kk^{-T} A(kb, b), 4 MFMAs
+    // each, and the trailing update A(a, b) -= R(kb, a)^T R(kb, b) 4 more.
+    T *Dt = sm + 2 * NP;
+    T *Yinv = Dt + Shared<T, NB>::TS;
+    constexpr int TS = Shared<T, NB>::TS;
     bool bad = false;
 #pragma unroll
     for (int kb = 0; kb < NB; ++kb) {
 #pragma unroll
+        for (int r = 0; r < 4; ++r) Dt[MF::row(g, r) * 17 + c] = A[TR::id(kb, kb)][r];
+        __syncthreads();
+        T p[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            p[i] = lane < 16 ? Dt[i * 17 + lane] : (i == (lane & 15) ? T(1) : T(0));
+#pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
-            const int k = 16 * kb + kk;
-            if (k < n_f) {
-                const int gk = MF::pivot_g(kk), rk = MF::pivot_r(kk);
-                T akk = readlane(A[TR::id(kb, kb)][rk], 16 * gk + kk);
-                if (!(akk > T(0))) {
+            if (16 * kb + kk < n_f) {
+                T d = readlane(p[kk], kk);
+                if (!(d > T(0))) {
                     bad = true;
-                    akk = T(1);
+                    d = T(1);
                 }
-                const T inv = T(1) / sqrt(akk);
+                p[kk] *= inv_sqrt(d);
+                T rk[16];  // row kk of the factor, broadcast first, then used
 #pragma unroll
-                for (int b = kb; b < NB; ++b) {
-                    if (g == gk) {
-                        const T v = A[TR::id(kb, b)][rk] * inv;
-                        A[TR::id(kb, b)][rk] = v;
-                        w[16 * b + c] = (16 * b + c > k) ? v : T(0);
-                    }
-                }
-                __syncthreads();
+                for (int i = kk + 1; i < 16; ++i) rk[i] = readlane(p[kk], i);
 #pragma unroll
-                for (int b = kb; b < NB; ++b) {
-                    const T cv = w[16 * b + c];
+                for (int i = kk + 1; i < 16; ++i) p[i] -= rk[i] * p[kk];
+            }
+        }
+        __syncthreads();
+        if (lane < 16) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) A[TR::id(kb, b)][r] -= w[16 * kb + MF::row(g, r)] * cv;
-                }
-                __syncthreads();
+            for (int i = 0; i < 16; ++i) Dt[i * 17 + lane] = p[i];
+        } else if (lane < 32) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Yinv[kb * TS + i * 17 + (lane - 16)] = p[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A[TR::id(kb, kb)][r] = Dt[MF::row(g, r) * 17 + c];
+        if (kb + 1 < NB) {
+            T aop[4];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) aop[s4] = Yinv[kb * TS + c * 17 + MF::row(g, s4)];
+#pragma unroll
+            for (int bb = kb + 1; bb < NB; ++bb) {
+                typename Mfma<T>::acc4 t = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) t = Mfma<T>::mma(aop[s4], A[TR::id(kb, bb)][s4], t);
+                A[TR::id(kb, bb)] = t;
             }
         }
 #pragma unroll
@@ -220,12 +250,15 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
 #pragma unroll
             for (int bb = a; bb < NB; ++bb)
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    A[TR::id(a, bb)] =
-                        Mfma<T>::mma(-A[TR::id(kb, a)][s], A[TR::id(kb, bb)][s], A[TR::id(a, bb)]);
+                for (int s4 = 0; s4 < 4; ++s4)
+                    A[TR::id(a, bb)] = Mfma<T>::mma(-A[TR::id(kb, a)][s4], A[TR::id(kb, bb)][s4],
+                                                    A[TR::id(a, bb)]);
+        __syncthreads();
     }
 
-    // ---- back substitution R x = z, z = column n_f of the factor
+    // ---- back substitution R x = z (z = column n_f of the factor), block by
+    // block from the last: z_kb -= R(kb, b) x_b for b > kb, x_kb = R_kk^{-1} z_kb
+    // = Y^T z_kb with the stored Y = R_kk^{-T}.
     if (c == caug) {
 #pragma unroll
         for (int a = 0; a < NB; ++a)
@@ -234,7 +267,6 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
     }
     for (int k = lane; k < NP; k += kWave) xs[k] = T(0);
     __syncthreads();
-    T myx = T(0);
 #pragma unroll
     for (int kb = NB - 1; kb >= 0; --kb) {
         if (16 * kb < n_f) {
@@ -245,32 +277,15 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
 #pragma unroll
                 for (int r = 0; r < 4; ++r) part[r] += A[TR::id(kb, bb)][r] * xv;
             }
+            T xp = T(0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                part[r] = sum16(part[r]);
-                Rs[MF::row(g, r) * 20 + c] = A[TR::id(kb, kb)][r];
+                const int i = MF::row(g, r);
+                const T z = (16 * kb + i < n_f) ? ys[16 * kb + i] - sum16(part[r]) : T(0);
+                xp += Yinv[kb * TS + i * 17 + c] * z;
             }
-            if (c == 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) zs[MF::row(g, r)] = ys[16 * kb + MF::row(g, r)] - part[r];
-            }
-            __syncthreads();
-            T Ri[16];
-            T zi = T(0);
-#pragma unroll
-            for (int q = 0; q < 16; ++q) Ri[q] = Rs[(lane & 15) * 20 + q];  // lanes >= 16: unused copies
-            zi = zs[lane & 15];
-#pragma unroll
-            for (int kk = 15; kk >= 0; --kk) {
-                if (16 * kb + kk < n_f) {
-                    const T zk = readlane(zi, kk);
-                    const T dk = readlane(Ri[kk], kk);
-                    const T xk = zk / dk;
-                    if (lane == kk) myx = xk;
-                    zi -= Ri[kk] * xk;
-                }
-            }
-            if (lane < 16 && 16 * kb + lane < n_f) xs[16 * kb + lane] = myx;
+            xp = sum4g(xp);
+            if (g == 0 && 16 * kb + c < n_f) xs[16 * kb + c] = xp;
             __syncthreads();
         }
     }
@@ -283,8 +298,14 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
 
 // One chunk per 64-lane workgroup.  chunk_row == nullptr: chunk q is row q
 // in full (fold-in and unplanned use).
+// Two resident wavefronts per SIMD where the tiles fit in 256 registers
+// (one runs its MFMA Gram while the other factorises).
+template <typename T, int NB> struct Occ {
+    static constexpr int waves = (sizeof(T) == 4 ? NB <= 7 : NB <= 4) ? 2 : 1;
+};
+
 template <typename T, int NB>
-__global__ __launch_bounds__(64) void sweep_chunks_kernel(
+__global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
     T lambda, int64_t n_chunks, const int32_t *__restrict__ chunk_row,
@@ -329,7 +350,7 @@ __global__ __launch_bounds__(64) void sweep_chunks_kernel(
 // Second stage for rows split over several chunks: fixed-order sum of the
 // partial Gram tiles, then the row solve.
 template <typename T, int NB>
-__global__ __launch_bounds__(64) void sweep_split_kernel(
+__global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_split_kernel(
     const int64_t *__restrict__ indptr, T *__restrict__ X, int n_f, int ld, T lambda,
     int64_t n_split, const int32_t *__restrict__ split_row, const int32_t *__restrict__ split_slot0,
     const int32_t *__restrict__ split_nslot, const typename Mfma<T>::acc4 *__restrict__ partial,
