@@ -11,10 +11,67 @@
 // enters f, ||g||^2 or the quartic coefficients is accumulated in FP64 and
 // stored as one partial per chunk (or per block), then summed in a fixed
 // order, so results are bitwise reproducible.
+#include <initializer_list>
+
 #include "internal.h"
 
 namespace alsncg {
 namespace {
+
+// ---------------------------------------------------------------- gathered rows
+//
+// Lane (g, c) of a wavefront handles rating t + g of each group of 4 and the
+// factor columns col(q) = (16 q + c) * VEC, ..., + VEC - 1 for q < NV: with
+// VEC = 4 a quarter-wave reads 256 contiguous bytes of a factor row per load
+// (FP32 rows whose length and stride are multiples of 4), with VEC = 1 it
+// reads 16 consecutive elements.
+template <typename T, int VEC> struct Vec {
+    typedef T type __attribute__((ext_vector_type(VEC)));
+};
+template <typename T> struct Vec<T, 1> {
+    typedef T type;
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ typename Vec<T, VEC>::type vzero() {
+    return typename Vec<T, VEC>::type(T(0));
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ T vdot(typename Vec<T, VEC>::type a, typename Vec<T, VEC>::type b) {
+    if constexpr (VEC == 1) {
+        return a * b;
+    } else {
+        T s = T(0);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) s += a[e] * b[e];
+        return s;
+    }
+}
+
+template <typename T, int VEC, int NV>
+__device__ __forceinline__ void load_row(typename Vec<T, VEC>::type (&v)[NV], const T *__restrict__ base,
+                                         int64_t j, int ld, int n_f, bool ok, int c) {
+    typedef typename Vec<T, VEC>::type V;
+    const T *row = base + j * ld;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int col = (16 * q + c) * VEC;
+        v[q] = (ok && col < n_f) ? *(const V *)(row + col) : vzero<T, VEC>();
+    }
+}
+
+template <typename T, int VEC, int NV>
+__device__ __forceinline__ void store_row(const typename Vec<T, VEC>::type (&v)[NV], T *__restrict__ base,
+                                          int64_t j, int ld, int n_f, int c) {
+    typedef typename Vec<T, VEC>::type V;
+    T *row = base + j * ld;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int col = (16 * q + c) * VEC;
+        if (col < n_f) *(V *)(row + col) = v[q];
+    }
+}
 
 // ---------------------------------------------------------------- gradient
 
@@ -23,8 +80,9 @@ namespace {
 //   G[i] = 2 lambda n_i X[i] + 2 sum_j Y[j] (X[i].Y[j] - r_ij).
 // scal[2q] receives this chunk's share of f, scal[2q + 1] of ||G||^2 (rows
 // that are whole in this chunk); split rows leave the regulariser and ||G||^2
-// to grad_split_kernel.
-template <typename T, int NBV>
+// to grad_split_kernel.  Rating ids are fetched two groups ahead and factor
+// rows one group ahead of their use.
+template <typename T, int VEC, int NV>
 __global__ __launch_bounds__(64) void grad_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ X, const T *__restrict__ Y, int n_f,
@@ -32,57 +90,72 @@ __global__ __launch_bounds__(64) void grad_chunks_kernel(
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ chunk_slot, T *__restrict__ G, T *__restrict__ partial,
     double *__restrict__ scal, int data_in_f, int want_g) {
+    typedef typename Vec<T, VEC>::type V;
     const int64_t q = blockIdx.x;
     if (q >= n_chunks) return;
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     const int64_t row = chunk_row[q], b = chunk_begin[q], e = b + chunk_len[q];
     const int slot = chunk_slot[q];
-    const T *xr = X + row * (int64_t)ld;
-    T x[NBV], acc[NBV];
+    V x[NV], acc[NV];
+    load_row<T, VEC, NV>(x, X, row, ld, n_f, true, c);
 #pragma unroll
-    for (int cb = 0; cb < NBV; ++cb) {
-        const int col = 16 * cb + c;
-        x[cb] = col < n_f ? xr[col] : T(0);
-        acc[cb] = T(0);
-    }
+    for (int k = 0; k < NV; ++k) acc[k] = vzero<T, VEC>();
     double e2 = 0.0;
-    for (int64_t t = b; t < e; t += 4) {
-        const int64_t p = t + g;
-        const bool ok = p < e;
-        const int j = ok ? idx[p] : 0;
-        const T r = ok ? (T)val[p] : T(0);
-        const T *yr = Y + (int64_t)j * ld;
-        T y[NBV];
-        T d = T(0);
+    if (b < e) {
+        V cur[NV];
+        bool okc = b + g < e;
+        T rc = okc ? (T)val[b + g] : T(0);
+        load_row<T, VEC, NV>(cur, Y, okc ? idx[b + g] : 0, ld, n_f, okc, c);
+        bool ok1 = b + 4 + g < e;
+        int j1 = ok1 ? idx[b + 4 + g] : 0;
+        T r1 = ok1 ? (T)val[b + 4 + g] : T(0);
+        for (int64_t t = b; t < e; t += 4) {
+            V nxt[NV];
+            load_row<T, VEC, NV>(nxt, Y, j1, ld, n_f, ok1, c);
+            const bool ok2 = t + 8 + g < e;
+            const int j2 = ok2 ? idx[t + 8 + g] : 0;
+            const T r2 = ok2 ? (T)val[t + 8 + g] : T(0);
+            T d = T(0);
 #pragma unroll
-        for (int cb = 0; cb < NBV; ++cb) {
-            const int col = 16 * cb + c;
-            y[cb] = (ok && col < n_f) ? yr[col] : T(0);
-            d += x[cb] * y[cb];
+            for (int k = 0; k < NV; ++k) d += vdot<T, VEC>(x[k], cur[k]);
+            d = sum16(d);
+            const T res = okc ? d - rc : T(0);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) acc[k] += res * cur[k];
+            if (c == 0) e2 += (double)res * (double)res;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) cur[k] = nxt[k];
+            okc = ok1;
+            rc = r1;
+            ok1 = ok2;
+            j1 = j2;
+            r1 = r2;
         }
-        d = sum16(d);
-        const T res = ok ? d - r : T(0);
-#pragma unroll
-        for (int cb = 0; cb < NBV; ++cb) acc[cb] += res * y[cb];
-        if (c == 0) e2 += (double)res * (double)res;
     }
 #pragma unroll
-    for (int cb = 0; cb < NBV; ++cb) acc[cb] = sum4g(acc[cb]);
+    for (int k = 0; k < NV; ++k) {
+        if constexpr (VEC == 1) {
+            acc[k] = sum4g(acc[k]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) acc[k][u] = sum4g(acc[k][u]);
+        }
+    }
     e2 = sum64(e2);
     if (slot < 0) {
         const int64_t n_i = indptr[row + 1] - indptr[row];
         const T reg2 = T(2.0 * lambda * (double)n_i);
         double gn = 0.0, xn = 0.0;
+        V gv[NV];
 #pragma unroll
-        for (int cb = 0; cb < NBV; ++cb) {
-            const int col = 16 * cb + c;
-            const T gv = T(2) * acc[cb] + reg2 * x[cb];
-            if (g == 0 && col < n_f) {
-                if (G) G[row * (int64_t)ld + col] = gv;
-                gn += (double)gv * (double)gv;
-                xn += (double)x[cb] * (double)x[cb];
+        for (int k = 0; k < NV; ++k) {
+            gv[k] = T(2) * acc[k] + reg2 * x[k];
+            if (g == 0) {
+                gn += (double)vdot<T, VEC>(gv[k], gv[k]);
+                xn += (double)vdot<T, VEC>(x[k], x[k]);
             }
         }
+        if (G && g == 0) store_row<T, VEC, NV>(gv, G, row, ld, n_f, c);
         gn = sum64(gn);
         xn = sum64(xn);
         if (lane == 0) {
@@ -90,10 +163,7 @@ __global__ __launch_bounds__(64) void grad_chunks_kernel(
             scal[2 * q + 1] = want_g ? gn : 0.0;
         }
     } else {
-        constexpr int NP = NBV * 16;
-#pragma unroll
-        for (int cb = 0; cb < NBV; ++cb)
-            if (g == 0) partial[(int64_t)slot * NP + 16 * cb + c] = acc[cb];
+        if (g == 0) store_row<T, VEC, NV>(acc, partial, slot, NV * 16 * VEC, n_f, c);
         if (lane == 0) {
             scal[2 * q] = data_in_f ? e2 : 0.0;
             scal[2 * q + 1] = 0.0;
@@ -101,13 +171,12 @@ __global__ __launch_bounds__(64) void grad_chunks_kernel(
     }
 }
 
-template <typename T, int NBV>
+template <typename T, int NP>
 __global__ __launch_bounds__(64) void grad_split_kernel(
     const int64_t *__restrict__ indptr, const T *__restrict__ X, int n_f, int ld, double lambda,
     int64_t n_split, const int32_t *__restrict__ split_row, const int32_t *__restrict__ split_slot0,
     const int32_t *__restrict__ split_nslot, const T *__restrict__ partial, T *__restrict__ G,
     double *__restrict__ scal, int want_g) {
-    constexpr int NP = NBV * 16;
     const int64_t s = blockIdx.x;
     if (s >= n_split) return;
     const int lane = threadIdx.x;
@@ -139,7 +208,7 @@ __global__ __launch_bounds__(64) void grad_split_kernel(
 //   (r - u.m)^2 = d^2 - 2 d a1 alpha + (a1^2 - 2 d a2) alpha^2 + 2 a1 a2 alpha^3 + a2^2 alpha^4.
 // The first chunk of each user row also adds that user's regulariser
 // lambda n_i ||xu + alpha pu||^2.  part[5q + n] is the chunk's share of C_n.
-template <typename T, int NBV>
+template <typename T, int VEC, int NV>
 __global__ __launch_bounds__(64) void coeff_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ XU, const T *__restrict__ XM,
@@ -147,46 +216,62 @@ __global__ __launch_bounds__(64) void coeff_chunks_kernel(
     int64_t n_chunks, const int32_t *__restrict__ chunk_row,
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
     double *__restrict__ part) {
+    typedef typename Vec<T, VEC>::type V;
     const int64_t q = blockIdx.x;
     if (q >= n_chunks) return;
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     const int64_t row = chunk_row[q], b = chunk_begin[q], e = b + chunk_len[q];
-    T xu[NBV], pu[NBV];
-#pragma unroll
-    for (int cb = 0; cb < NBV; ++cb) {
-        const int col = 16 * cb + c;
-        xu[cb] = col < n_f ? XU[row * (int64_t)ld + col] : T(0);
-        pu[cb] = col < n_f ? PU[row * (int64_t)ld + col] : T(0);
-    }
+    V xu[NV], pu[NV];
+    load_row<T, VEC, NV>(xu, XU, row, ld, n_f, true, c);
+    load_row<T, VEC, NV>(pu, PU, row, ld, n_f, true, c);
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
-    for (int64_t t = b; t < e; t += 4) {
-        const int64_t p = t + g;
-        const bool ok = p < e;
-        const int j = ok ? idx[p] : 0;
-        const float r = ok ? val[p] : 0.0f;
-        const T *xmr = XM + (int64_t)j * ld;
-        const T *pmr = PM + (int64_t)j * ld;
-        T a0 = T(0), a1 = T(0), a2 = T(0);
-#pragma unroll
-        for (int cb = 0; cb < NBV; ++cb) {
-            const int col = 16 * cb + c;
-            const bool in = ok && col < n_f;
-            const T xm = in ? xmr[col] : T(0);
-            const T pm = in ? pmr[col] : T(0);
-            a0 += xu[cb] * xm;
-            a1 += xu[cb] * pm + pu[cb] * xm;
-            a2 += pu[cb] * pm;
+    if (b < e) {
+        V xc[NV], pc[NV];
+        bool okc = b + g < e;
+        float rc = okc ? val[b + g] : 0.0f;
+        {
+            const int j0 = okc ? idx[b + g] : 0;
+            load_row<T, VEC, NV>(xc, XM, j0, ld, n_f, okc, c);
+            load_row<T, VEC, NV>(pc, PM, j0, ld, n_f, okc, c);
         }
-        a0 = sum16(a0);
-        a1 = sum16(a1);
-        a2 = sum16(a2);
-        if (ok && c == 0) {
-            const double d = (double)r - (double)a0, A1 = (double)a1, A2 = (double)a2;
-            c0 += d * d;
-            c1 += -2.0 * d * A1;
-            c2 += A1 * A1 - 2.0 * d * A2;
-            c3 += 2.0 * A1 * A2;
-            c4 += A2 * A2;
+        bool ok1 = b + 4 + g < e;
+        int j1 = ok1 ? idx[b + 4 + g] : 0;
+        float r1 = ok1 ? val[b + 4 + g] : 0.0f;
+        for (int64_t t = b; t < e; t += 4) {
+            V xn[NV], pn[NV];
+            load_row<T, VEC, NV>(xn, XM, j1, ld, n_f, ok1, c);
+            load_row<T, VEC, NV>(pn, PM, j1, ld, n_f, ok1, c);
+            const bool ok2 = t + 8 + g < e;
+            const int j2 = ok2 ? idx[t + 8 + g] : 0;
+            const float r2 = ok2 ? val[t + 8 + g] : 0.0f;
+            T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                a0 += vdot<T, VEC>(xu[k], xc[k]);
+                a1 += vdot<T, VEC>(xu[k], pc[k]) + vdot<T, VEC>(pu[k], xc[k]);
+                a2 += vdot<T, VEC>(pu[k], pc[k]);
+            }
+            a0 = sum16(a0);
+            a1 = sum16(a1);
+            a2 = sum16(a2);
+            if (okc && c == 0) {
+                const double d = (double)rc - (double)a0, A1 = (double)a1, A2 = (double)a2;
+                c0 += d * d;
+                c1 += -2.0 * d * A1;
+                c2 += A1 * A1 - 2.0 * d * A2;
+                c3 += 2.0 * A1 * A2;
+                c4 += A2 * A2;
+            }
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                xc[k] = xn[k];
+                pc[k] = pn[k];
+            }
+            okc = ok1;
+            rc = r1;
+            ok1 = ok2;
+            j1 = j2;
+            r1 = r2;
         }
     }
     c0 = sum64(c0);
@@ -197,11 +282,11 @@ __global__ __launch_bounds__(64) void coeff_chunks_kernel(
     if (b == indptr[row]) {
         double xx = 0.0, xp = 0.0, pp = 0.0;
 #pragma unroll
-        for (int cb = 0; cb < NBV; ++cb)
+        for (int k = 0; k < NV; ++k)
             if (g == 0) {
-                xx += (double)xu[cb] * (double)xu[cb];
-                xp += (double)xu[cb] * (double)pu[cb];
-                pp += (double)pu[cb] * (double)pu[cb];
+                xx += (double)vdot<T, VEC>(xu[k], xu[k]);
+                xp += (double)vdot<T, VEC>(xu[k], pu[k]);
+                pp += (double)vdot<T, VEC>(pu[k], pu[k]);
             }
         xx = sum64(xx);
         xp = sum64(xp);
@@ -285,11 +370,11 @@ __global__ __launch_bounds__(256) void coeff_itemreg_kernel(const int64_t *__res
 
 constexpr int kItemBlocks = 512;
 
-template <typename T, int NBV>
+template <typename T, int VEC, int NV>
 int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
                  const T *U, const T *M, int n_f, int ld, double lambda, T *gU, T *gM,
                  double *out2, hipStream_t s) {
-    constexpr int NP = NBV * 16;
+    constexpr int NP = NV * 16 * VEC;
     const bool doR = (gU != nullptr) || (out2 != nullptr);
     const bool doRt = (gM != nullptr) || (out2 != nullptr);
     const int64_t rowsR = doR ? pR->n_chunks + pR->n_split_rows : 0;
@@ -305,12 +390,12 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
     T *partRt = (T *)(ws + scal_bytes + pR_bytes);
     if (doR) {
         if (pR->n_chunks)
-            hipLaunchKernelGGL((grad_chunks_kernel<T, NBV>), dim3((unsigned)pR->n_chunks), dim3(kWave),
-                               0, s, R->indptr, R->indices, R->values, U, M, n_f, ld, lambda,
-                               pR->n_chunks, pR->chunk_row, pR->chunk_begin, pR->chunk_len,
+            hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV>), dim3((unsigned)pR->n_chunks),
+                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, U, M, n_f, ld,
+                               lambda, pR->n_chunks, pR->chunk_row, pR->chunk_begin, pR->chunk_len,
                                pR->chunk_slot, gU, partR, scal, 1, gU != nullptr ? 1 : 0);
         if (pR->n_split_rows)
-            hipLaunchKernelGGL((grad_split_kernel<T, NBV>), dim3((unsigned)pR->n_split_rows),
+            hipLaunchKernelGGL((grad_split_kernel<T, NP>), dim3((unsigned)pR->n_split_rows),
                                dim3(kWave), 0, s, R->indptr, U, n_f, ld, lambda, pR->n_split_rows,
                                pR->split_row, pR->split_slot0, pR->split_nslot, partR, gU,
                                scal + 2 * pR->n_chunks, gU != nullptr ? 1 : 0);
@@ -318,25 +403,23 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
     if (doRt) {
         double *sc = scal + 2 * rowsR;
         if (pRt->n_chunks)
-            hipLaunchKernelGGL((grad_chunks_kernel<T, NBV>), dim3((unsigned)pRt->n_chunks),
+            hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV>), dim3((unsigned)pRt->n_chunks),
                                dim3(kWave), 0, s, Rt->indptr, Rt->indices, Rt->values, M, U, n_f,
                                ld, lambda, pRt->n_chunks, pRt->chunk_row, pRt->chunk_begin,
                                pRt->chunk_len, pRt->chunk_slot, gM, partRt, sc, 0,
                                gM != nullptr ? 1 : 0);
         if (pRt->n_split_rows)
-            hipLaunchKernelGGL((grad_split_kernel<T, NBV>), dim3((unsigned)pRt->n_split_rows),
+            hipLaunchKernelGGL((grad_split_kernel<T, NP>), dim3((unsigned)pRt->n_split_rows),
                                dim3(kWave), 0, s, Rt->indptr, M, n_f, ld, lambda,
                                pRt->n_split_rows, pRt->split_row, pRt->split_slot0,
                                pRt->split_nslot, partRt, gM, sc + 2 * pRt->n_chunks,
                                gM != nullptr ? 1 : 0);
     }
-    if (out2) {
-        launch_sum_columns(scal, rowsR + rowsRt, 2, out2, 0, s);
-    }
+    if (out2) launch_sum_columns(scal, rowsR + rowsRt, 2, out2, 0, s);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
-template <typename T, int NBV>
+template <typename T, int VEC, int NV>
 int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const T *U,
                const T *M, const T *PU, const T *PM, int n_f, int ld, double lambda,
                double *coeffs, hipStream_t s) {
@@ -345,10 +428,11 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
     double *part = (double *)ctx->workspace((size_t)rows * 5 * sizeof(double), s, &err);
     if (!part) return err;
     if (pR->n_chunks)
-        hipLaunchKernelGGL((coeff_chunks_kernel<T, NBV>), dim3((unsigned)pR->n_chunks), dim3(kWave),
-                           0, s, R->indptr, R->indices, R->values, U, M, PU, PM, n_f, ld, lambda,
-                           pR->n_chunks, pR->chunk_row, pR->chunk_begin, pR->chunk_len, part);
-    hipLaunchKernelGGL((coeff_itemreg_kernel<T, NBV>), dim3(kItemBlocks), dim3(256), 0, s,
+        hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV>), dim3((unsigned)pR->n_chunks),
+                           dim3(kWave), 0, s, R->indptr, R->indices, R->values, U, M, PU, PM, n_f,
+                           ld, lambda, pR->n_chunks, pR->chunk_row, pR->chunk_begin,
+                           pR->chunk_len, part);
+    hipLaunchKernelGGL((coeff_itemreg_kernel<T, NV * VEC>), dim3(kItemBlocks), dim3(256), 0, s,
                        Rt->indptr, Rt->n_rows, M, PM, n_f, ld, lambda, part + 5 * pR->n_chunks);
     launch_sum_columns(part, rows, 5, coeffs, 0, s);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
@@ -368,31 +452,62 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
         default: return ALS_E_INVAL; \
     }
 
+// FP32 rows of length and stride divisible by 4 on 16-byte boundaries are
+// gathered 4 elements per lane; everything else one element per lane.
+static bool vec4_ok(int n_f, int ld, std::initializer_list<const void *> ptrs) {
+    if (n_f % 4 != 0 || ld % 4 != 0) return false;
+    for (const void *p : ptrs)
+        if (p && ((uintptr_t)p % 16) != 0) return false;
+    return true;
+}
+
 }  // namespace
 
 int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
                     const void *U, const void *M, int n_f, int ld, double lambda, als_dtype dt,
                     void *gU, void *gM, double *out2, hipStream_t s) {
+#define GA(T, VEC, NV) \
+    return run_gradient<T, VEC, NV>(ctx, pR, R, pRt, Rt, (const T *)U, (const T *)M, n_f, ld, lambda, (T *)gU, (T *)gM, out2, s)
+    if (dt == ALS_F32 && vec4_ok(n_f, ld, {U, M, gU, gM})) {
+        switch ((n_f + 63) / 64) {
+            case 1: GA(float, 4, 1);
+            case 2: GA(float, 4, 2);
+            case 3: GA(float, 4, 3);
+            default: return ALS_E_INVAL;
+        }
+    }
+#define G32(N) GA(float, 1, N)
+#define G64(N) GA(double, 1, N)
     const int nbv = (n_f + 15) / 16;
-#define G32(N) return run_gradient<float, N>(ctx, pR, R, pRt, Rt, (const float *)U, (const float *)M, n_f, ld, lambda, (float *)gU, (float *)gM, out2, s)
-#define G64(N) return run_gradient<double, N>(ctx, pR, R, pRt, Rt, (const double *)U, (const double *)M, n_f, ld, lambda, (double *)gU, (double *)gM, out2, s)
     if (dt == ALS_F32) { ALS_NBV_SWITCH(nbv, G32) }
     if (dt == ALS_F64) { ALS_NBV_SWITCH(nbv, G64) }
 #undef G32
 #undef G64
+#undef GA
     return ALS_E_INVAL;
 }
 
 int launch_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const void *U,
                   const void *M, const void *pU, const void *pM, int n_f, int ld, double lambda,
                   als_dtype dt, double *coeffs, hipStream_t s) {
+#define CA(T, VEC, NV) \
+    return run_coeffs<T, VEC, NV>(ctx, pR, R, Rt, (const T *)U, (const T *)M, (const T *)pU, (const T *)pM, n_f, ld, lambda, coeffs, s)
+    if (dt == ALS_F32 && vec4_ok(n_f, ld, {U, M, pU, pM})) {
+        switch ((n_f + 63) / 64) {
+            case 1: CA(float, 4, 1);
+            case 2: CA(float, 4, 2);
+            case 3: CA(float, 4, 3);
+            default: return ALS_E_INVAL;
+        }
+    }
+#define C32(N) CA(float, 1, N)
+#define C64(N) CA(double, 1, N)
     const int nbv = (n_f + 15) / 16;
-#define C32(N) return run_coeffs<float, N>(ctx, pR, R, Rt, (const float *)U, (const float *)M, (const float *)pU, (const float *)pM, n_f, ld, lambda, coeffs, s)
-#define C64(N) return run_coeffs<double, N>(ctx, pR, R, Rt, (const double *)U, (const double *)M, (const double *)pU, (const double *)pM, n_f, ld, lambda, coeffs, s)
     if (dt == ALS_F32) { ALS_NBV_SWITCH(nbv, C32) }
     if (dt == ALS_F64) { ALS_NBV_SWITCH(nbv, C64) }
 #undef C32
 #undef C64
+#undef CA
     return ALS_E_INVAL;
 }
 

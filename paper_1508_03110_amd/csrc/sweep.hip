@@ -45,54 +45,148 @@ template <typename T, int NB> struct Shared {
     static constexpr int size = 2 * NP + TS + NB * TS;
 };
 
-// Gathered operand of one group of 4 ratings: lane (g, c) holds column
-// 16 cb + c of the factor row of rating t + g (the rating itself in column n_f).
+// Slot order of the Gram matrix.  Slot s = 16 cb + c (tile block cb, lane
+// column c) holds factor column pi(s):
+//   blocks 0 .. 4Q-1      : pi = 64 q + 4 c + e   (cb = 4 q + e)  -- one 16-byte load per lane
+//   blocks 4Q .. 4Q+2P-1  : pi = 64 Q + 2 c + e  (cb = 4 Q + e)  -- one 8-byte load
+//   remaining blocks      : pi = s                                 -- one 4-byte load each
+// with Q = floor((NB-1)/4) and P = 1 when 64 Q + 32 <= 16 (NB-1).  For
+// NB = ceil((n_f+1)/16) every column of the first two groups is a real factor
+// column, so slots 0..n_f-1 are the n_f factor columns (in permuted order),
+// slot n_f is the rating (the augmented column) and the rest is zero padding:
+// a symmetric permutation of the real block, which the factorisation does not
+// care about; only the row's input and output go through pi.
+template <int NB> struct Slots {
+    static constexpr int Q = (NB - 1) / 4;
+    static constexpr int P = (64 * Q + 32 <= 16 * (NB - 1)) ? 1 : 0;
+    __host__ __device__ static constexpr int col(int s) {
+        return (s >> 4) < 4 * Q ? 64 * ((s >> 4) >> 2) + 4 * (s & 15) + ((s >> 4) & 3)
+               : (s >> 4) < 4 * Q + 2 * P ? 64 * Q + 2 * (s & 15) + ((s >> 4) - 4 * Q)
+                                          : s;
+    }
+};
+
+// Raw gathered operand of one group of 4 ratings: lane (g, c) loads slot
+// 16 cb + c of the factor row j of rating t + g.  The load is unconditional
+// (j is 0 for ratings past the end of the chunk and columns past n_f are
+// clamped into the row) so that no branch or mask sits between a load and its
+// use; finish_operand() applies the masks when the MFMAs consume the values.
+// vec: the row may be read with 16- and 8-byte loads (FP32, 16-byte aligned).
 template <typename T, int NB>
-__device__ __forceinline__ void gather_row(T (&gv)[NB], const T *__restrict__ Y, int j, bool ok,
-                                           T r, int ld, int n_f, int c) {
+__device__ __forceinline__ void gather_row(T (&gv)[NB], const T *__restrict__ Y, int j, int ld,
+                                           int n_f, int c, bool vec) {
+    typedef Slots<NB> SL;
     const T *row = Y + (int64_t)j * ld;
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) {
+    for (int q = 0; q < SL::Q; ++q) {
+        const T *p4 = row + 64 * q + 4 * c;
+        if constexpr (sizeof(T) == 4) {
+            if (vec) {
+                typedef float f4 __attribute__((ext_vector_type(4)));
+                const f4 v = *(const f4 *)p4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) gv[4 * q + e] = v[e];
+                continue;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) gv[4 * q + e] = p4[e];
+    }
+    if constexpr (SL::P == 1) {
+        const T *p2 = row + 64 * SL::Q + 2 * c;
+        bool done = false;
+        if constexpr (sizeof(T) == 4) {
+            if (vec) {
+                typedef float f2 __attribute__((ext_vector_type(2)));
+                const f2 v = *(const f2 *)p2;
+                gv[4 * SL::Q] = v[0];
+                gv[4 * SL::Q + 1] = v[1];
+                done = true;
+            }
+        }
+        if (!done) {
+            gv[4 * SL::Q] = p2[0];
+            gv[4 * SL::Q + 1] = p2[1];
+        }
+    }
+#pragma unroll
+    for (int cb = 4 * SL::Q + 2 * SL::P; cb < NB; ++cb) {
         const int col = cb * 16 + c;
-        T v = T(0);
-        if (ok && col < n_f) v = row[col];
-        gv[cb] = (col == n_f) ? r : v;
+        gv[cb] = row[col < n_f ? col : n_f - 1];
     }
 }
 
-// Gram accumulation over ratings [b, e) of one row, software-pipelined:
-// rating ids two groups ahead, factor rows one group ahead of the MFMAs.
+// Masks of a gathered operand: zero for ratings past the chunk end, the
+// rating value in slot n_f, zero in padding slots.
+template <typename T, int NB>
+__device__ __forceinline__ void finish_operand(T (&gv)[NB], bool ok, T r, int n_f, int c) {
+    typedef Slots<NB> SL;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+        if (cb < 4 * SL::Q + 2 * SL::P) {
+            gv[cb] = ok ? gv[cb] : T(0);
+        } else {
+            const int col = cb * 16 + c;
+            gv[cb] = (col < n_f) ? (ok ? gv[cb] : T(0)) : (col == n_f ? r : T(0));
+        }
+    }
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void gram_update(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
+                                            const T (&gv)[NB]) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int bb = a; bb < NB; ++bb)
+            A[Tri<NB>::id(a, bb)] = Mfma<T>::mma(gv[a], gv[bb], A[Tri<NB>::id(a, bb)]);
+}
+
+// Gram accumulation over ratings [b, e) of one row.  Two register buffers
+// alternate: while the MFMAs consume group s, the factor rows of group s + 1
+// and the rating id of group s + 2 are in flight.  The loop body covers two
+// groups so that no register is copied between a load and its use (a copy
+// would force the wait for the load right after issuing it), and has a single
+// exit (exits in the middle make the allocator duplicate the accumulators).
+// Loads for groups past the end read valid addresses and are discarded.
 template <typename T, int NB>
 __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
                                                 const int32_t *__restrict__ idx,
                                                 const float *__restrict__ val, int64_t b, int64_t e,
                                                 const T *__restrict__ Y, int ld, int n_f, int g,
-                                                int c) {
+                                                int c, bool vec) {
     if (b >= e) return;
-    T cur[NB];
-    {
-        const int64_t p = b + g;
-        const bool ok = p < e;
-        gather_row<T, NB>(cur, Y, ok ? idx[p] : 0, ok, ok ? (T)val[p] : T(0), ld, n_f, c);
+    const int last = (int)(e - 1 - b);
+    const int ng = (last >> 2) + 1;
+    const int32_t *ix = idx + b;
+    const float *vx = val + b;
+    T buf0[NB], buf1[NB];
+    int p = min(g, last);
+    float r0 = vx[p];
+    gather_row<T, NB>(buf0, Y, ix[p], ld, n_f, c, vec);
+    p = min(4 + g, last);
+    int j1 = ix[p];
+    float r1 = vx[p];
+    int s = 0;
+    for (; s + 1 < ng; s += 2) {
+        gather_row<T, NB>(buf1, Y, j1, ld, n_f, c, vec);
+        p = min(4 * (s + 2) + g, last);
+        const int j0 = ix[p];
+        const float rn0 = vx[p];
+        finish_operand<T, NB>(buf0, 4 * s + g <= last, (T)r0, n_f, c);
+        gram_update<T, NB>(A, buf0);
+        gather_row<T, NB>(buf0, Y, j0, ld, n_f, c, vec);
+        p = min(4 * (s + 3) + g, last);
+        j1 = ix[p];
+        const float rn1 = vx[p];
+        finish_operand<T, NB>(buf1, 4 * (s + 1) + g <= last, (T)r1, n_f, c);
+        gram_update<T, NB>(A, buf1);
+        r0 = rn0;
+        r1 = rn1;
     }
-    int64_t p1 = b + 4 + g;
-    bool ok1 = p1 < e;
-    int j1 = ok1 ? idx[p1] : 0;
-    T r1 = ok1 ? (T)val[p1] : T(0);
-    for (int64_t t = b; t < e; t += 4) {
-        T nxt[NB];
-        gather_row<T, NB>(nxt, Y, j1, ok1, r1, ld, n_f, c);
-        const int64_t p2 = t + 8 + g;
-        ok1 = p2 < e;
-        j1 = ok1 ? idx[p2] : 0;
-        r1 = ok1 ? (T)val[p2] : T(0);
-#pragma unroll
-        for (int a = 0; a < NB; ++a)
-#pragma unroll
-            for (int bb = a; bb < NB; ++bb)
-                A[Tri<NB>::id(a, bb)] = Mfma<T>::mma(cur[a], cur[bb], A[Tri<NB>::id(a, bb)]);
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) cur[cb] = nxt[cb];
+    if (s < ng) {
+        finish_operand<T, NB>(buf0, 4 * s + g <= last, (T)r0, n_f, c);
+        gram_update<T, NB>(A, buf0);
     }
 }
 
@@ -134,39 +228,34 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
     if (grad_out) {
         // y = A x_in (A symmetric, upper tiles only), then g = 2 (y - v).
         const T *xin = X_at ? X_at + row * (int64_t)ld : xrow;
-        for (int k = lane; k < NP; k += kWave) xs[k] = (k < n_f) ? xin[k] : T(0);
+        for (int k = lane; k < NP; k += kWave) xs[k] = (k < n_f) ? xin[Slots<NB>::col(k)] : T(0);
         __syncthreads();
-        T racc[NB][4];
+        // row-block a of A x: tiles (a, b >= a) times x_b, reduced over the 16
+        // lanes of a quarter-wave as soon as the block row is done; the
+        // transposed contributions of the upper tiles to block b collect in cacc
         T cacc[NB];
 #pragma unroll
+        for (int a = 0; a < NB; ++a) cacc[a] = T(0);
+#pragma unroll
         for (int a = 0; a < NB; ++a) {
-            cacc[a] = T(0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) racc[a][r] = T(0);
-        }
-#pragma unroll
-        for (int a = 0; a < NB; ++a)
+            T racc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int bb = a; bb < NB; ++bb) {
                 const T xv = xs[16 * bb + c];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    racc[a][r] += A[TR::id(a, bb)][r] * xv;
+                    racc[r] += A[TR::id(a, bb)][r] * xv;
                     if (a < bb) cacc[bb] += A[TR::id(a, bb)][r] * xs[16 * a + MF::row(g, r)];
                 }
             }
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-            cacc[a] = sum4g(cacc[a]);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) racc[a][r] = sum16(racc[a][r]);
+            for (int r = 0; r < 4; ++r) {
+                const T v = sum16(racc[r]);
+                if (c == 0) ys[16 * a + MF::row(g, r)] = v;
+            }
         }
-        if (c == 0) {
 #pragma unroll
-            for (int a = 0; a < NB; ++a)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) ys[16 * a + MF::row(g, r)] = racc[a][r];
-        }
+        for (int a = 0; a < NB; ++a) cacc[a] = sum4g(cacc[a]);
         if (c == caug) {
 #pragma unroll
             for (int a = 0; a < NB; ++a)
@@ -180,7 +269,7 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
         }
         __syncthreads();
         for (int k = lane; k < n_f; k += kWave)
-            grad_out[row * (int64_t)ld + k] = T(2) * (ys[k] - w[k]);
+            grad_out[row * (int64_t)ld + Slots<NB>::col(k)] = T(2) * (ys[k] - w[k]);
         __syncthreads();
     }
 
@@ -289,7 +378,7 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
             __syncthreads();
         }
     }
-    for (int k = lane; k < n_f; k += kWave) xrow[k] = bad ? T(NAN) : xs[k];
+    for (int k = lane; k < n_f; k += kWave) xrow[Slots<NB>::col(k)] = bad ? T(NAN) : xs[k];
     if (lane == 0) {
         if (bad && bad_row) atomicMin((unsigned long long *)bad_row, (unsigned long long)row);
         if (status) status[row] = bad ? (int32_t)ALS_E_NOT_SPD : 0;
@@ -312,7 +401,7 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ chunk_slot, typename Mfma<T>::acc4 *__restrict__ partial,
     const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row,
-    int32_t *__restrict__ status, int empty_status) {
+    int32_t *__restrict__ status, int empty_status, int vec) {
     typedef typename Mfma<T>::acc4 acc4;
     typedef Tri<NB> TR;
     __shared__ T sm[Shared<T, NB>::size];
@@ -335,7 +424,7 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     acc4 A[TR::NT];
 #pragma unroll
     for (int t = 0; t < TR::NT; ++t) A[t] = acc4{T(0), T(0), T(0), T(0)};
-    gram_accumulate<T, NB>(A, idx, val, b, b + len, Y, ld, n_f, g, c);
+    gram_accumulate<T, NB>(A, idx, val, b, b + len, Y, ld, n_f, g, c, vec != 0);
     if (slot >= 0) {
         acc4 *dst = partial + (int64_t)slot * TR::NT * kWave;
 #pragma unroll
@@ -384,13 +473,14 @@ int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, in
               int64_t n_rows_unplanned, hipStream_t s) {
     typedef typename Mfma<T>::acc4 acc4;
     typedef Tri<NB> TR;
+    const int vec = sizeof(T) == 4 && ld % 4 == 0 && ((uintptr_t)Y % 16) == 0;
     if (bad_row) hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, bad_row, (int64_t)LLONG_MAX);
     if (!plan) {
         if (n_rows_unplanned > 0)
             hipLaunchKernelGGL((sweep_chunks_kernel<T, NB>), dim3((unsigned)n_rows_unplanned),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
                                lambda, n_rows_unplanned, nullptr, nullptr, nullptr, nullptr,
-                               (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status);
+                               (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status, vec);
         return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
     }
     acc4 *partial = nullptr;
@@ -404,7 +494,7 @@ int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, in
                            0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld, lambda,
                            plan->n_chunks, plan->chunk_row, plan->chunk_begin, plan->chunk_len,
                            plan->chunk_slot, partial, X_at, grad_out, bad_row, status,
-                           empty_status);
+                           empty_status, vec);
     if (plan->n_split_rows > 0)
         hipLaunchKernelGGL((sweep_split_kernel<T, NB>), dim3((unsigned)plan->n_split_rows),
                            dim3(kWave), 0, s, R->indptr, X, n_f, ld, lambda, plan->n_split_rows,

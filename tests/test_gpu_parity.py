@@ -108,18 +108,27 @@ def test_sweep_random_shapes(ctx, dtype, n_f):
         assert fro(Xg, ref) <= TOL[dtype]["fro"], chunk
 
 
-def test_sweep_padded_leading_dimension(ctx):
-    """ld > n_f: padding columns are neither read nor written."""
-    P = synth.random_problem(50, 40, n_f=10, lam=0.05, seed=9, density=0.3, x0_sigma=0.5)
-    ld = 13
+@pytest.mark.parametrize("dtype,n_f,ld", [(torch.float64, 10, 13), (torch.float64, 50, 53),
+                                         (torch.float32, 100, 101), (torch.float32, 100, 104),
+                                         (torch.float32, 64, 66)])
+def test_sweep_padded_leading_dimension(ctx, dtype, n_f, ld):
+    """ld > n_f: padding columns are neither read nor written (ld % 4 == 0
+    takes the vector-gather path for FP32, other strides the scalar one)."""
+    P = synth.random_problem(50, 40, n_f=n_f, lam=0.05, seed=9, density=0.3, x0_sigma=0.5)
     Y = np.full((P.n_m, ld), 7.0)
-    Y[:, :10] = P.M0
-    X = torch.full((P.n_u, ld), -3.0, dtype=torch.float64, device=ctx.torch_device)
-    DP = dev_problem(ctx, P, torch.float64, ld=ld)
-    DP.sweep("U", to_dev(Y, torch.float64, ctx), X)
-    Xg = host(X)
-    assert np.all(Xg[:, 10:] == -3.0)
-    assert fro(Xg[:, :10], oracle.half_sweep(P.R, P.M0, P.lam)) <= 1e-12
+    Y[:, :n_f] = P.M0 if dtype == torch.float64 else r32(P.M0)
+    X = torch.full((P.n_u, ld), -3.0, dtype=dtype, device=ctx.torch_device)
+    DP = dev_problem(ctx, P, dtype, ld=ld)
+    G = torch.full((P.n_u, ld), -5.0, dtype=dtype, device=ctx.torch_device)
+    Xat = torch.zeros((P.n_u, ld), dtype=dtype, device=ctx.torch_device)
+    Xat[:, :n_f] = to_dev(P.U0 if dtype == torch.float64 else r32(P.U0), dtype, ctx)
+    DP.sweep("U", to_dev(Y, dtype, ctx), X, X_at=Xat, grad_out=G)
+    Xg, Gg = host(X), host(G)
+    assert np.all(Xg[:, n_f:] == -3.0) and np.all(Gg[:, n_f:] == -5.0)
+    Yr = Y[:, :n_f]
+    assert fro(Xg[:, :n_f], oracle.half_sweep(P.R, Yr, P.lam)) <= TOL[dtype]["fro"]
+    gU, _ = oracle.gradient(P.R, P.Rt, host(Xat)[:, :n_f], Yr, P.lam)
+    assert fro(Gg[:, :n_f], gU) <= (1e-12 if dtype == torch.float64 else 2e-5)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -175,8 +184,11 @@ def test_sweep_is_deterministic(ctx, c0):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("chunk", [0, 8])
-def test_gradient_and_loss(ctx, dtype, chunk):
-    P = synth.random_problem(90, 70, n_f=20, lam=0.07, seed=21, density=0.15, long_rows=2,
+@pytest.mark.parametrize("n_f", [20, 50, 100])
+def test_gradient_and_loss(ctx, dtype, chunk, n_f):
+    """Both gradient blocks and f; n_f = 20 and 100 take the 4-wide FP32
+    gather path, n_f = 50 the one-element path."""
+    P = synth.random_problem(90, 70, n_f=n_f, lam=0.07, seed=21, density=0.15, long_rows=2,
                              empty_rows=3, x0_sigma=0.5)
     U0 = P.U0 if dtype == torch.float64 else r32(P.U0)
     M0 = P.M0 if dtype == torch.float64 else r32(P.M0)
