@@ -141,11 +141,12 @@ int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void 
                      const void *g_old, void *p, double *scal, int restart, int pr_plus,
                      als_dtype dt, hipStream_t s);
 
-// Deterministic FP64 column sums of a row-major [rows, cols] array (one
-// workgroup, fixed order).  out[k] = sum_r parts[r * cols + k] (+ out[k] when
-// accumulate != 0).
+// Deterministic FP64 column sums of a row-major [rows, cols] array, cols <= 8
+// (two launches, fixed order).  out[k] = sum_r parts[r * cols + k] (+ out[k]
+// when accumulate != 0).  stage: device scratch of kSumStageDoubles doubles.
+constexpr int kSumStageDoubles = 256 * 8;
 void launch_sum_columns(const double *parts, int64_t rows, int cols, double *out, int accumulate,
-                        hipStream_t s);
+                        double *stage, hipStream_t s);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -379,7 +379,8 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
     const bool doRt = (gM != nullptr) || (out2 != nullptr);
     const int64_t rowsR = doR ? pR->n_chunks + pR->n_split_rows : 0;
     const int64_t rowsRt = doRt ? pRt->n_chunks + pRt->n_split_rows : 0;
-    const size_t scal_bytes = align_up((size_t)(rowsR + rowsRt + 1) * 2 * sizeof(double), 256);
+    const size_t scal_bytes =
+        align_up((size_t)((rowsR + rowsRt + 1) * 2 + kSumStageDoubles) * sizeof(double), 256);
     const size_t pR_bytes = doR ? align_up((size_t)pR->n_slots * NP * sizeof(T) + 16, 256) : 0;
     const size_t pRt_bytes = doRt ? align_up((size_t)pRt->n_slots * NP * sizeof(T) + 16, 256) : 0;
     int err = ALS_OK;
@@ -415,7 +416,8 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
                                pRt->split_nslot, partRt, gM, sc + 2 * pRt->n_chunks,
                                gM != nullptr ? 1 : 0);
     }
-    if (out2) launch_sum_columns(scal, rowsR + rowsRt, 2, out2, 0, s);
+    if (out2)
+        launch_sum_columns(scal, rowsR + rowsRt, 2, out2, 0, scal + (rowsR + rowsRt + 1) * 2, s);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
@@ -425,7 +427,8 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
                double *coeffs, hipStream_t s) {
     const int64_t rows = pR->n_chunks + kItemBlocks;
     int err = ALS_OK;
-    double *part = (double *)ctx->workspace((size_t)rows * 5 * sizeof(double), s, &err);
+    double *part =
+        (double *)ctx->workspace((size_t)(rows * 5 + kSumStageDoubles) * sizeof(double), s, &err);
     if (!part) return err;
     if (pR->n_chunks)
         hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV>), dim3((unsigned)pR->n_chunks),
@@ -434,7 +437,7 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
                            pR->chunk_len, part);
     hipLaunchKernelGGL((coeff_itemreg_kernel<T, NV * VEC>), dim3(kItemBlocks), dim3(256), 0, s,
                        Rt->indptr, Rt->n_rows, M, PM, n_f, ld, lambda, part + 5 * pR->n_chunks);
-    launch_sum_columns(part, rows, 5, coeffs, 0, s);
+    launch_sum_columns(part, rows, 5, coeffs, 0, part + rows * 5, s);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 

@@ -17,23 +17,54 @@ constexpr int kVecBlocks = 2048;  // fixed: the reduction order must not depend 
 
 // ---------------------------------------------------------------- reductions
 
-__global__ __launch_bounds__(1024) void sum_columns_kernel(const double *__restrict__ parts,
-                                                           int64_t rows, int cols,
-                                                           double *__restrict__ out,
-                                                           int accumulate) {
-    __shared__ double red[1024];
-    for (int k = 0; k < cols; ++k) {
-        double s = 0.0;
-        for (int64_t r = threadIdx.x; r < rows; r += 1024) s += parts[r * cols + k];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[k] = accumulate ? out[k] + red[0] : red[0];
+constexpr int kSumBlocks = 256;
+constexpr int kSumThreads = 256;
+constexpr int kMaxCols = 8;
+
+// Stage 1: block k sums rows [k R / B, (k + 1) R / B) of every column into
+// stage[k * cols + c]; stage 2 (one block) sums the B partials.  The split of
+// the rows depends only on R, so the result is the same on every run.
+__global__ __launch_bounds__(kSumThreads) void sum_columns_stage1(const double *__restrict__ parts,
+                                                                  int64_t rows, int cols,
+                                                                  double *__restrict__ stage) {
+    __shared__ double red[kMaxCols][kSumThreads];
+    const int64_t r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
+    double acc[kMaxCols];
+#pragma unroll
+    for (int k = 0; k < kMaxCols; ++k) acc[k] = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += kSumThreads)
+#pragma unroll
+        for (int k = 0; k < kMaxCols; ++k)
+            if (k < cols) acc[k] += parts[r * cols + k];
+#pragma unroll
+    for (int k = 0; k < kMaxCols; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < kMaxCols; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
         __syncthreads();
     }
+    if ((int)threadIdx.x < cols) stage[(int64_t)blockIdx.x * cols + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kSumThreads) void sum_columns_stage2(const double *__restrict__ stage,
+                                                                  int nblocks, int cols,
+                                                                  double *__restrict__ out,
+                                                                  int accumulate) {
+    __shared__ double red[kMaxCols][kSumThreads];
+#pragma unroll
+    for (int k = 0; k < kMaxCols; ++k)
+        red[k][threadIdx.x] = (k < cols && (int)threadIdx.x < nblocks) ? stage[threadIdx.x * cols + k] : 0.0;
+    __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < kMaxCols; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < cols)
+        out[threadIdx.x] = accumulate ? out[threadIdx.x] + red[threadIdx.x][0] : red[threadIdx.x][0];
 }
 
 template <int NV>
@@ -155,9 +186,11 @@ __global__ void backtrack_kernel(const double *__restrict__ C, double alpha0, do
 }  // namespace
 
 void launch_sum_columns(const double *parts, int64_t rows, int cols, double *out, int accumulate,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(sum_columns_kernel, dim3(1), dim3(1024), 0, s, parts, rows, cols, out,
-                       accumulate);
+                        double *stage, hipStream_t s) {
+    hipLaunchKernelGGL(sum_columns_stage1, dim3(kSumBlocks), dim3(kSumThreads), 0, s, parts, rows,
+                       cols, stage);
+    hipLaunchKernelGGL(sum_columns_stage2, dim3(1), dim3(kSumThreads), 0, s, stage, kSumBlocks,
+                       cols, out, accumulate);
 }
 
 int launch_backtrack(const double *coeffs, double alpha0, double tau, double c, int max_trials,
@@ -204,9 +237,11 @@ int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void 
                      const void *g_old, void *p, double *scal, int restart, int pr_plus,
                      als_dtype dt, hipStream_t s) {
     int err = ALS_OK;
-    double *part = (double *)ctx->workspace((size_t)(kVecBlocks * 3 + 8) * sizeof(double), s, &err);
+    double *part = (double *)ctx->workspace(
+        (size_t)(kVecBlocks * 3 + 8 + kSumStageDoubles) * sizeof(double), s, &err);
     if (!part) return err;
     double *sums = part + kVecBlocks * 3;
+    double *stage = sums + 8;
     // fixed grid so the reduction order is the same for every n
     const unsigned grid = kVecBlocks;
     if (dt == ALS_F32)
@@ -219,7 +254,7 @@ int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void 
                            restart ? nullptr : (const double *)g_old, part);
     else
         return ALS_E_INVAL;
-    launch_sum_columns(part, kVecBlocks, 3, sums, 0, s);
+    launch_sum_columns(part, kVecBlocks, 3, sums, 0, stage, s);
     hipLaunchKernelGGL(direction_beta_kernel, dim3(1), dim3(1), 0, s, sums, scal, restart, pr_plus);
     if (dt == ALS_F32)
         hipLaunchKernelGGL(direction_update_kernel<float>, dim3(vec_grid(n)), dim3(kVecThreads), 0,
