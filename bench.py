@@ -90,12 +90,55 @@ def cpu_baseline(P):
                       % (P.nnz, P.n_f, dt, t_init)}
 
 
+def serve_bench(ctx, M_dev, P, rates=(10_000, 50_000, 200_000), duration=2.0, warm=0.5,
+                baseline_cap=20_000, seed=4):
+    """Fold-in serving: open-loop Poisson arrivals replayed in real time by the
+    native server; latency = result visible on the host - arrival."""
+    import numpy as np
+
+    import synth
+    from paper_1508_03110_amd.solver import FoldInServer
+    t0 = time.perf_counter()
+    pool = synth.fold_in_requests(16384, P.n_m, seed=seed, item_perm=P.meta["item_perm"],
+                                  M_star=P.meta["M_star"])
+    log("request pool: %d requests, %d ratings, mean %.1f (%.1f s)"
+        % (pool.n_rows, pool.nnz, pool.nnz / pool.n_rows, time.perf_counter() - t0))
+    rng = np.random.default_rng(seed + 1)
+    configs = {"continuous_batching": dict(max_inflight=4, max_batch=4096, split=256),
+               "one_request_per_launch": dict(max_inflight=1, max_batch=1, split=0)}
+    out = {"pool_requests": pool.n_rows, "mean_ratings": pool.nnz / pool.n_rows,
+           "duration_s": duration, "warmup_s": warm, "hbm_budget_bytes": 16 << 30}
+    for name, cfg in configs.items():
+        srv = FoldInServer(ctx, M_dev, P.lam, P.n_f, budget_bytes=16 << 30, **cfg)
+        res = {}
+        for rate in rates:
+            n = int(rate * (duration + warm))
+            if name == "one_request_per_launch":
+                n = min(n, baseline_cap)
+            arrival = np.cumsum(rng.exponential(1e9 / rate, size=n)).astype(np.int64)
+            rows = rng.integers(0, pool.n_rows, size=n).astype(np.int32)
+            comp, st, _ = srv.replay(arrival, rows, pool)
+            keep = arrival >= (warm * 1e9 if n * 1e9 / rate > 2 * warm * 1e9 else 0)
+            lat = (comp - arrival)[keep] / 1e6
+            span = (comp[keep].max() - arrival[keep].min()) / 1e9
+            res[str(rate)] = {"requests": int(keep.sum()), "p50_ms": float(np.percentile(lat, 50)),
+                              "p99_ms": float(np.percentile(lat, 99)),
+                              "solves_per_s": float(keep.sum() / max(span, 1e-9)),
+                              "errors": int((st != 0).sum())}
+            log("serve %s @%d req/s: %s" % (name, rate, res[str(rate)]))
+        srv.close()
+        out[name] = {"config": cfg, "rates": res}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the fold-in serving measurement")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -183,6 +226,11 @@ def main():
         "f": solver.f,
         "gnorm_over_N": solver.gnorm() / (P.n_f * (P.n_u + P.n_m)),
     }
+    if not args.no_serve:
+        M_dev = DP.M(solver.x)[:, : P.n_f].contiguous()
+        result["fold_in"] = serve_bench(ctx, M_dev, P, duration=args.serve_seconds)
+        p99 = {r: v["p99_ms"] for r, v in result["fold_in"]["continuous_batching"]["rates"].items()}
+        result["fold_in_p99_ms"] = p99
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

@@ -224,6 +224,66 @@ ALS_API int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int l
             als_dtype dt, int64_t n_req, const int64_t *req_indptr, const int32_t *req_items,
             const float *req_vals, void *U_out, int32_t *req_status, void *stream);
 
+/* ---------------------------------------------------------------- serving
+ *
+ * Fold-in server: new users (requests) are solved against fixed item factors
+ * by the row solve of Eq. (3), with continuous batching.  Requests wait in a
+ * FIFO queue; whenever one of `max_inflight` batch slots is free, every queued
+ * request that fits the slot is admitted into one batch, which is copied to
+ * the device, solved (long requests split over several wavefronts, fixed-order
+ * reduction) and copied back on the slot's own stream, so batches overlap on
+ * the device while new requests keep arriving.  Device memory is bounded by
+ * `hbm_budget_bytes` (split evenly over the slots); a request too large for a
+ * slot is answered with ALS_E_BUDGET, never dropped.  A request's result does
+ * not depend on which other requests share its batch.  One server per host
+ * thread; M must stay valid and unchanged while the server lives.
+ */
+typedef struct als_server als_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes; /* device bytes for all slots (inputs, plans, results, workspace) */
+    int32_t max_inflight;     /* batch slots (each with its own stream), >= 1 */
+    int32_t max_batch;        /* requests per batch, >= 1 (1 = one request per launch) */
+    int32_t split;            /* ratings per wavefront for long requests (0: one wavefront each) */
+} als_server_config;
+
+/* Create a server solving against M [n_items, ld] (device, FP32 or FP64). */
+ALS_API int als_server_create(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int ld,
+                              double lambda, als_dtype dt, const als_server_config *cfg,
+                              als_server **out);
+/* Waits for in-flight batches, then frees everything.  NULL is ignored. */
+ALS_API void als_server_destroy(als_server *srv);
+
+/* Queue n requests (host arrays, copied by the call): request q has id
+ * ids[q] and ratings (items[k], vals[k]) for k in [indptr[q], indptr[q+1]),
+ * item ids in [0, n_items), distinct within a request. */
+ALS_API int als_server_submit(als_server *srv, int64_t n, const int64_t *ids, const int64_t *indptr,
+                              const int32_t *items, const float *vals);
+
+/* Non-blocking progress: harvest finished batches and admit queued requests
+ * into free slots.  Reports at most max_done finished requests: done_ids,
+ * done_status (0, ALS_E_INVAL for an empty request, ALS_E_NOT_SPD,
+ * ALS_E_BUDGET) and their solutions in done_U (host, row-major
+ * [max_done, n_f], element type dt); *n_done receives the count. */
+ALS_API int als_server_poll(als_server *srv, int64_t max_done, int64_t *done_ids,
+                            int32_t *done_status, void *done_U, int64_t *n_done);
+
+/* Number of requests queued or in flight. */
+ALS_API int64_t als_server_pending(const als_server *srv);
+
+/* Open-loop replay for latency measurement: arrival q carries request
+ * pool_row[q] of a request pool (host CSR pool_indptr [n_pool+1], pool_items,
+ * pool_vals) and becomes visible to the server arrival_ns[q] nanoseconds
+ * after the call starts (non-decreasing); the call spins on the server's
+ * admission and harvesting until every arrival is answered.  completion_ns[q]
+ * receives the time its result was visible on the host, status[q] (may be
+ * NULL) its status, U_out (host [n, n_f], may be NULL) its solution.  The
+ * server must be idle (nothing queued or in flight). */
+ALS_API int als_server_replay(als_server *srv, int64_t n, const int64_t *arrival_ns,
+                              const int32_t *pool_row, int64_t n_pool, const int64_t *pool_indptr,
+                              const int32_t *pool_items, const float *pool_vals,
+                              int64_t *completion_ns, int32_t *status, void *U_out);
+
 #ifdef __cplusplus
 }
 #endif

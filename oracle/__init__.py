@@ -31,7 +31,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "als_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB = os.environ.get("ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 
 # line-search constants of Section V-C (tau, c, alpha_0)
 TAU = 0.9
@@ -44,7 +44,10 @@ def build(force: bool = False) -> str:
     """Compile als_oracle.c with gcc (double precision, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+        # ORACLE_CFLAGS (e.g. "-O3 -march=native") only changes code generation;
+        # -ffp-contract=off keeps every product and sum separately rounded.
+        extra = os.environ.get("ORACLE_CFLAGS", "-O2").split()
+        subprocess.check_call(["gcc"] + extra + ["-std=c11", "-fopenmp", "-fPIC", "-shared",
                                "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

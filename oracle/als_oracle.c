@@ -116,10 +116,12 @@ int orc_half_sweep(int64_t n_rows, const int64_t *indptr, const int32_t *indices
                 const double *y = Y + (int64_t)indices[t] * n_f;
                 double r = vals[t];
                 for (int p = 0; p < n_f; ++p) {
-                    for (int q = 0; q < n_f; ++q) A[p * n_f + q] += y[p] * y[q];
+                    for (int q = p; q < n_f; ++q) A[p * n_f + q] += y[p] * y[q];
                     v[p] += r * y[p];
                 }
             }
+            for (int p = 0; p < n_f; ++p)       /* A is symmetric: mirror the upper triangle */
+                for (int q = 0; q < p; ++q) A[p * n_f + q] = A[q * n_f + p];
             double reg = lambda * (double)(e - b);
             for (int p = 0; p < n_f; ++p) A[p * n_f + p] += reg;
             if (cholesky(A, n_f) != 0) {

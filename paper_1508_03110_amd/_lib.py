@@ -31,6 +31,12 @@ class Csr(ctypes.Structure):
                 ("values", ctypes.c_void_p)]
 
 
+class ServerConfig(ctypes.Structure):
+    """als_server_config."""
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("split", ctypes.c_int32)]
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _i64 = ctypes.c_int64
@@ -55,6 +61,13 @@ _SIGS = {
     "ncg_axpby": (_i, [_vp, _i64, _d, _vp, _d, _vp, _i, _vp]),
     "ncg_direction": (_i, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp]),
     "fold_in": (_i, [_vp, _vp, _i64, _i, _i, _d, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "als_server_create": (_i, [_vp, _vp, _i64, _i, _i, _d, _i, ctypes.POINTER(ServerConfig),
+                               ctypes.POINTER(_vp)]),
+    "als_server_destroy": (None, [_vp]),
+    "als_server_submit": (_i, [_vp, _i64, _vp, _vp, _vp, _vp]),
+    "als_server_poll": (_i, [_vp, _i64, _vp, _vp, _vp, ctypes.POINTER(_i64)]),
+    "als_server_pending": (_i64, [_vp]),
+    "als_server_replay": (_i, [_vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -199,3 +212,46 @@ def fold_in(ctx, M, n_items, n_f, ld, lam, dt, n_req, req_indptr, req_items, req
                                             int(dt), int(n_req), _ptr(req_indptr), _ptr(req_items),
                                             _ptr(req_vals), _ptr(U_out), _ptr(req_status),
                                             _stream(stream)))
+
+
+# ---------------------------------------------------------------- fold-in server
+
+def _hp(a):
+    """Host pointer of a contiguous numpy array (or None)."""
+    return None if a is None else a.ctypes.data
+
+
+def als_server_create(ctx, M, n_items, n_f, ld, lam, dt, cfg: ServerConfig):
+    out = _vp()
+    _check("als_server_create", load().als_server_create(ctx, _ptr(M), int(n_items), int(n_f), int(ld),
+                                                         float(lam), int(dt), ctypes.byref(cfg),
+                                                         ctypes.byref(out)))
+    return out.value
+
+
+def als_server_destroy(srv):
+    load().als_server_destroy(srv)
+
+
+def als_server_submit(srv, ids, indptr, items, vals):
+    return _check("als_server_submit", load().als_server_submit(srv, int(len(ids)), _hp(ids), _hp(indptr),
+                                                                _hp(items), _hp(vals)))
+
+
+def als_server_poll(srv, max_done, done_ids, done_status, done_U):
+    n = _i64(0)
+    _check("als_server_poll", load().als_server_poll(srv, int(max_done), _hp(done_ids), _hp(done_status),
+                                                     _hp(done_U), ctypes.byref(n)))
+    return int(n.value)
+
+
+def als_server_pending(srv) -> int:
+    return int(load().als_server_pending(srv))
+
+
+def als_server_replay(srv, arrival_ns, pool_row, pool_indptr, pool_items, pool_vals, completion_ns,
+                      status=None, U_out=None):
+    return _check("als_server_replay", load().als_server_replay(
+        srv, int(len(arrival_ns)), _hp(arrival_ns), _hp(pool_row), int(len(pool_indptr) - 1),
+        _hp(pool_indptr), _hp(pool_items), _hp(pool_vals), _hp(completion_ns), _hp(status),
+        _hp(U_out)))

@@ -125,6 +125,13 @@ int launch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, vo
 int launch_fold_in(Ctx *ctx, const void *M, int n_f, int ld, double lambda, als_dtype dt,
                    int64_t n_req, const int64_t *indptr, const int32_t *items, const float *vals,
                    void *U_out, int32_t *status, hipStream_t s);
+// Planned half-sweep over a caller-built plan with caller-provided split-K
+// workspace (sweep_partial_bytes per split chunk) and per-row status (empty
+// row: ALS_E_INVAL, not SPD: ALS_E_NOT_SPD, else 0).  Used by the fold-in
+// server, which builds one plan per batch.
+size_t sweep_partial_bytes(int n_f, als_dtype dt);
+int launch_sweep_batch(const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f, int ld,
+                       double lambda, als_dtype dt, void *partial, int32_t *status, hipStream_t s);
 int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
                     const void *U, const void *M, int n_f, int ld, double lambda, als_dtype dt,
                     void *gU, void *gM, double *out2, hipStream_t s);

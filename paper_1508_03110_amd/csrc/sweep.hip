@@ -443,7 +443,8 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_split_kernel(
     const int64_t *__restrict__ indptr, T *__restrict__ X, int n_f, int ld, T lambda,
     int64_t n_split, const int32_t *__restrict__ split_row, const int32_t *__restrict__ split_slot0,
     const int32_t *__restrict__ split_nslot, const typename Mfma<T>::acc4 *__restrict__ partial,
-    const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row) {
+    const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row,
+    int32_t *__restrict__ status) {
     typedef typename Mfma<T>::acc4 acc4;
     typedef Tri<NB> TR;
     __shared__ T sm[Shared<T, NB>::size];
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_split_kernel(
         for (int t = 0; t < TR::NT; ++t) A[t] += src[t * kWave + lane];
     }
     const int64_t n_i = indptr[row + 1] - indptr[row];
-    finish_row<T, NB>(A, row, n_i, X, n_f, ld, lambda, X_at, grad_out, bad_row, nullptr, 0, sm);
+    finish_row<T, NB>(A, row, n_i, X, n_f, ld, lambda, X_at, grad_out, bad_row, status, 0, sm);
 }
 
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
@@ -470,7 +471,7 @@ __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 template <typename T, int NB>
 int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
               T lambda, const T *X_at, T *grad_out, int64_t *bad_row, int32_t *status, int empty_status,
-              int64_t n_rows_unplanned, hipStream_t s) {
+              int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
     typedef typename Mfma<T>::acc4 acc4;
     typedef Tri<NB> TR;
     const int vec = sizeof(T) == 4 && ld % 4 == 0 && ((uintptr_t)Y % 16) == 0;
@@ -483,8 +484,8 @@ int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, in
                                (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status, vec);
         return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
     }
-    acc4 *partial = nullptr;
-    if (plan->n_slots > 0) {
+    acc4 *partial = (acc4 *)partial_ext;
+    if (plan->n_slots > 0 && !partial) {
         int err = ALS_OK;
         partial = (acc4 *)ctx->workspace((size_t)plan->n_slots * TR::NT * kWave * sizeof(acc4), s, &err);
         if (!partial) return err;
@@ -499,20 +500,20 @@ int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, in
         hipLaunchKernelGGL((sweep_split_kernel<T, NB>), dim3((unsigned)plan->n_split_rows),
                            dim3(kWave), 0, s, R->indptr, X, n_f, ld, lambda, plan->n_split_rows,
                            plan->split_row, plan->split_slot0, plan->split_nslot, partial, X_at,
-                           grad_out, bad_row);
+                           grad_out, bad_row, status);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
 template <typename T>
 int dispatch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f,
                    int ld, double lambda, const void *X_at, void *grad_out, int64_t *bad_row, int32_t *status,
-                   int empty_status, int64_t n_rows_unplanned, hipStream_t s) {
+                   int empty_status, int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
     const int nb = (n_f + 1 + 15) / 16;
 #define ALS_SWEEP_CASE(NBV)                                                                      \
     case NBV:                                                                                    \
         return run_sweep<T, NBV>(ctx, plan, R, (const T *)Y, (T *)X, n_f, ld, (T)lambda,         \
                                  (const T *)X_at, (T *)grad_out, bad_row, status, empty_status, n_rows_unplanned, \
-                                 s);
+                                 partial_ext, s);
     if constexpr (sizeof(T) == 4) {
         switch (nb) {
             ALS_SWEEP_CASE(1)
@@ -547,10 +548,10 @@ int launch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, vo
                  int64_t *bad_row, hipStream_t s) {
     if (dt == ALS_F32)
         return dispatch_sweep<float>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out, bad_row,
-                                     nullptr, 0, 0, s);
+                                     nullptr, 0, 0, nullptr, s);
     if (dt == ALS_F64)
         return dispatch_sweep<double>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out,
-                                      bad_row, nullptr, 0, 0, s);
+                                      bad_row, nullptr, 0, 0, nullptr, s);
     return ALS_E_INVAL;
 }
 
@@ -566,10 +567,28 @@ int launch_fold_in(Ctx *ctx, const void *M, int n_f, int ld, double lambda, als_
     R.values = vals;
     if (dt == ALS_F32)
         return dispatch_sweep<float>(ctx, nullptr, &R, M, U_out, n_f, ld, lambda, nullptr, nullptr,
-                                     nullptr, status, ALS_E_INVAL, n_req, s);
+                                     nullptr, status, ALS_E_INVAL, n_req, nullptr, s);
     if (dt == ALS_F64)
         return dispatch_sweep<double>(ctx, nullptr, &R, M, U_out, n_f, ld, lambda, nullptr,
-                                      nullptr, nullptr, status, ALS_E_INVAL, n_req, s);
+                                      nullptr, nullptr, status, ALS_E_INVAL, n_req, nullptr, s);
+    return ALS_E_INVAL;
+}
+
+size_t sweep_partial_bytes(int n_f, als_dtype dt) {
+    const size_t nb = (size_t)(n_f + 1 + 15) / 16;
+    const size_t nt = nb * (nb + 1) / 2;
+    return nt * kWave * 4 * (dt == ALS_F64 ? sizeof(double) : sizeof(float));
+}
+
+int launch_sweep_batch(const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f, int ld,
+                       double lambda, als_dtype dt, void *partial, int32_t *status,
+                       hipStream_t s) {
+    if (dt == ALS_F32)
+        return dispatch_sweep<float>(nullptr, plan, R, Y, X, n_f, ld, lambda, nullptr, nullptr,
+                                     nullptr, status, ALS_E_INVAL, 0, partial, s);
+    if (dt == ALS_F64)
+        return dispatch_sweep<double>(nullptr, plan, R, Y, X, n_f, ld, lambda, nullptr, nullptr,
+                                      nullptr, status, ALS_E_INVAL, 0, partial, s);
     return ALS_E_INVAL;
 }
 

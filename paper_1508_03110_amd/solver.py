@@ -301,3 +301,71 @@ def fold_in(ctx: Context, M, lam: float, req, n_f: int, ld: Optional[int] = None
     st = torch.zeros(n_req, dtype=torch.int32, device=dev)
     L.fold_in(ctx.handle, M, M.shape[0], n_f, ld, lam, L.dtype_code(M.dtype), n_req, ip, it, va, U, st)
     return U, st
+
+
+class FoldInServer:
+    """Continuous-batching fold-in server (als_server_*) against device item
+    factors M [n_items, ld]; host numpy in, host numpy out."""
+
+    def __init__(self, ctx: Context, M, lam: float, n_f: int, budget_bytes: int = 16 << 30,
+                 max_inflight: int = 4, max_batch: int = 4096, split: int = 256):
+        self.ctx, self.M, self.n_f = ctx, M, int(n_f)
+        self.np_dtype = np.float64 if M.dtype == torch.float64 else np.float32
+        cfg = L.ServerConfig(int(budget_bytes), int(max_inflight), int(max_batch), int(split))
+        self.handle = L.als_server_create(ctx.handle, M, M.shape[0], n_f, M.shape[1], lam,
+                                          L.dtype_code(M.dtype), cfg)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.als_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, ids, req):
+        """Queue the rows of host CSR `req` with the given ids."""
+        L.als_server_submit(self.handle, np.ascontiguousarray(ids, dtype=np.int64),
+                            np.ascontiguousarray(req.indptr, dtype=np.int64),
+                            np.ascontiguousarray(req.indices, dtype=np.int32),
+                            np.ascontiguousarray(req.values, dtype=np.float32))
+
+    def poll(self, max_done: int = 4096):
+        ids = np.empty(max_done, np.int64)
+        st = np.empty(max_done, np.int32)
+        U = np.empty((max_done, self.n_f), self.np_dtype)
+        n = L.als_server_poll(self.handle, max_done, ids, st, U)
+        return ids[:n], st[:n], U[:n]
+
+    def pending(self) -> int:
+        return L.als_server_pending(self.handle)
+
+    def drain(self, timeout_s: float = 60.0):
+        """Poll until nothing is queued or in flight; returns all results."""
+        import time
+        out_ids, out_st, out_U = [], [], []
+        t0 = time.time()
+        while True:
+            ids, st, U = self.poll()
+            out_ids.append(ids); out_st.append(st); out_U.append(U)
+            if self.pending() == 0 and len(ids) == 0:
+                break
+            if time.time() - t0 > timeout_s:
+                raise TimeoutError("fold-in server did not drain")
+        return np.concatenate(out_ids), np.concatenate(out_st), np.concatenate(out_U)
+
+    def replay(self, arrival_ns, pool_row, pool, want_U: bool = False):
+        """Open-loop replay (als_server_replay); returns (completion_ns, status, U|None)."""
+        n = len(arrival_ns)
+        comp = np.empty(n, np.int64)
+        st = np.empty(n, np.int32)
+        U = np.empty((n, self.n_f), self.np_dtype) if want_U else None
+        L.als_server_replay(self.handle, np.ascontiguousarray(arrival_ns, dtype=np.int64),
+                            np.ascontiguousarray(pool_row, dtype=np.int32),
+                            np.ascontiguousarray(pool.indptr, dtype=np.int64),
+                            np.ascontiguousarray(pool.indices, dtype=np.int32),
+                            np.ascontiguousarray(pool.values, dtype=np.float32), comp, st, U)
+        return comp, st, U
