@@ -34,7 +34,9 @@
  *  - Regularisation is always the paper's count-weighted lambda * n_i of
  *    Eq. (1) (n_i = number of ratings of row i); lambda >= 0.
  *  - Element type of factor and vector arguments is selected by `dt`:
- *    ALS_F64 (double), ALS_F32 (float).  ALS_BF16 is reserved.
+ *    ALS_F64 (double), ALS_F32 (float).  ALS_BF16 (bfloat16, stored as
+ *    16-bit words) appears only in the reduced-precision calls
+ *    als_sweep_mixed / als_to_bf16.
  */
 #ifndef ALSNCG_H
 #define ALSNCG_H
@@ -131,6 +133,33 @@ ALS_API int als_plan_info(const als_plan *plan, int64_t out[7]);
 ALS_API int als_sweep(als_ctx *ctx, const als_plan *plan, const als_csr *R, const void *Y, void *X,
                       int n_f, int ld, double lambda, als_dtype dt, const void *X_at,
                       void *grad_out, int64_t *bad_row, void *stream);
+
+/*
+ * Reduced-precision ALS half-sweep: the row solve of Eq. (3) (Eq. (4) for
+ * R^T) with the fixed factor read from a BF16 copy.  For every row i:
+ *     A~_i = sum_j y~_j y~_j^T + lambda n_i I,  v~_i = sum_j bf16(r_ij) y~_j,
+ *     x0 = A~_i^{-1} v~_i        (y~_j = Y16[j]; Gram on BF16 MFMA with FP32
+ *                                 accumulation, Cholesky and solves in FP32)
+ * and, when refine != 0, one step of iterative refinement with the residual
+ * of the FP32 normal equations (y_j = Y32[j], FP32 ratings):
+ *     x1 = x0 + A~_i^{-1} ( sum_j (r_ij - y_j . x0) y_j - lambda n_i x0 ).
+ * The result is written to X32 [R->n_rows, ld] (float) and, when X16 is not
+ * NULL, rounded to nearest even into X16 [R->n_rows, ld] (bfloat16 words).
+ *   Y16: [R->n_cols, ld] bfloat16 words (the BF16 copy of the fixed factor);
+ *   Y32: [R->n_cols, ld] float, the same factor in FP32 (required when
+ *        refine != 0, else may be NULL).
+ *   bad_row: as in als_sweep.  Rows with n_i = 0 get 0.
+ * Loads are 16-byte vectors when ld is a multiple of 8 and Y16 is 16-byte
+ * aligned (element loads otherwise).  n_f: 1..143.  A plan is required.  The
+ * outputs must not overlap the inputs.
+ */
+ALS_API int als_sweep_mixed(als_ctx *ctx, const als_plan *plan, const als_csr *R, const void *Y16,
+                            const float *Y32, float *X32, void *X16, int n_f, int ld,
+                            double lambda, int refine, int64_t *bad_row, void *stream);
+
+/* y[k] = bf16(x[k]) (round to nearest even) for k < n; x float, y bfloat16
+ * words; the BF16 copy of a factor read by als_sweep_mixed. */
+ALS_API int als_to_bf16(als_ctx *ctx, int64_t n, const float *x, void *y, void *stream);
 
 /*
  * Gradient of Eq. (1) (Section III-A; Section V-C, gradient evaluation):

@@ -7,6 +7,9 @@ lives in ``als_oracle.c`` (plain C, double precision); this module adds the
 outer algorithms in numpy float64:
 
 * ``als_sweep``      -- one ALS iteration P(x), Algorithm 1 (Section III-A);
+* ``mixed_half_sweep`` -- the row solve of Eq. (3) on bfloat16 copies of the
+                        fixed factor, with an optional refinement step
+                        against the FP32 normal equations;
 * ``backtrack``      -- backtracking line search on the quartic, Algorithm 4
                         with tau = 0.9, c = 0.5, alpha_0 = 10 (Section V-C);
 * ``NcgOracle``      -- ALS-NCG, Algorithm 2 with the preconditioned
@@ -163,6 +166,55 @@ def quartic(R, U, M, PU, PM, lam: float) -> np.ndarray:
                         _p(R.values, _f64p), _p(U, _f64p), _p(M, _f64p), _p(PU, _f64p),
                         _p(PM, _f64p), U.shape[1], float(lam), _p(C, _f64p))
     return C
+
+
+# ----------------------------------------------------------------------------
+# reduced-precision half-sweep (the row solve of Eq. (3) on bfloat16 copies)
+# ----------------------------------------------------------------------------
+
+def bf16_round(x) -> np.ndarray:
+    """Nearest bfloat16 value of each FP32 input, ties to even, as float64.
+
+    bfloat16 is the upper half of an IEEE binary32 word (sign, 8 exponent
+    bits, 7 stored mantissa bits).  Rounding adds half a unit of the dropped
+    16 bits, plus one when the kept part is odd and the dropped part is
+    exactly half (round half to even); a mantissa carry moves into the
+    exponent, as it should.  Inputs must be finite."""
+    a = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    half = np.uint64(0x7FFF) + ((a >> np.uint64(16)) & np.uint64(1))
+    kept = ((a + half) >> np.uint64(16)) << np.uint64(16)
+    return kept.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mixed_half_sweep(A, Y32: np.ndarray, lam: float, refine: bool) -> np.ndarray:
+    """Row solve of Eq. (3) (Eq. (4) for R^T) on bfloat16 copies, in FP64.
+
+    For each row i with ratings (j, r_ij):
+        At = sum_j yt_j yt_j^T + lam n_i I,   vt = sum_j bf16(r_ij) yt_j,
+        x0 = At^{-1} vt                         (yt_j = bf16(Y32[j]))
+    and with refine, one refinement step against the unrounded normal
+    equations A x = v of Eq. (3):
+        x1 = x0 + At^{-1} (v - A x0),  v - A x0 = sum_j (r_ij - y_j.x0) y_j - lam n_i x0.
+    Rows without ratings are 0.  Dense per-row solves (numpy); tiny inputs only."""
+    Y = _f64(np.asarray(Y32, dtype=np.float32))
+    Yt = bf16_round(Y32).reshape(Y.shape)
+    n_f = Y.shape[1]
+    X = np.zeros((A.n_rows, n_f), dtype=np.float64)
+    for i in range(A.n_rows):
+        lo, hi = int(A.indptr[i]), int(A.indptr[i + 1])
+        n = hi - lo
+        if n == 0:
+            continue
+        ids = np.asarray(A.indices[lo:hi])
+        r = np.asarray(A.values[lo:hi], dtype=np.float32)
+        Gt = Yt[ids].T @ Yt[ids] + lam * n * np.eye(n_f)
+        x = np.linalg.solve(Gt, Yt[ids].T @ bf16_round(r))
+        if refine:
+            Yi = Y[ids]
+            res = Yi.T @ (r.astype(np.float64) - Yi @ x) - lam * n * x
+            x = x + np.linalg.solve(Gt, res)
+        X[i] = x
+    return X
 
 
 # ----------------------------------------------------------------------------

@@ -52,6 +52,8 @@ _SIGS = {
     "als_plan_destroy": (None, [_vp]),
     "als_plan_info": (_i, [_vp, ctypes.POINTER(_i64)]),
     "als_sweep": (_i, [_vp, _vp, _csrp, _vp, _vp, _i, _i, _d, _i, _vp, _vp, _vp, _vp]),
+    "als_sweep_mixed": (_i, [_vp, _vp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _vp, _vp]),
+    "als_to_bf16": (_i, [_vp, _i64, _vp, _vp, _vp]),
     "ncg_gradient": (_i, [_vp, _vp, _csrp, _vp, _csrp, _vp, _vp, _i, _i, _d, _i, _vp, _vp, _vp,
                           _vp]),
     "linesearch_coeffs": (_i, [_vp, _vp, _csrp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _vp,
@@ -166,6 +168,17 @@ def als_sweep(ctx, plan, R: Csr, Y, X, n_f, ld, lam, dt, X_at=None, grad_out=Non
     return _check("als_sweep", load().als_sweep(ctx, plan, ctypes.byref(R), _ptr(Y), _ptr(X), int(n_f),
                                                 int(ld), float(lam), int(dt), _ptr(X_at),
                                                 _ptr(grad_out), _ptr(bad_row), _stream(stream)))
+
+
+def als_sweep_mixed(ctx, plan, R: Csr, Y16, Y32, X32, X16, n_f, ld, lam, refine, bad_row=None,
+                    stream=None):
+    return _check("als_sweep_mixed", load().als_sweep_mixed(
+        ctx, plan, ctypes.byref(R), _ptr(Y16), _ptr(Y32), _ptr(X32), _ptr(X16), int(n_f), int(ld),
+        float(lam), 1 if refine else 0, _ptr(bad_row), _stream(stream)))
+
+
+def als_to_bf16(ctx, n, x, y, stream=None):
+    return _check("als_to_bf16", load().als_to_bf16(ctx, int(n), _ptr(x), _ptr(y), _stream(stream)))
 
 
 def ncg_gradient(ctx, plan_R, R: Csr, plan_Rt, Rt: Csr, U, M, n_f, ld, lam, dt, gU=None, gM=None,

@@ -119,7 +119,7 @@ size_t als_ctx_workspace_bytes(const als_ctx *ctx) { return ctx ? ctx->ws_bytes 
 void als_plan_destroy(als_plan *p) {
     if (!p) return;
     void *bufs[] = {p->chunk_row, p->chunk_begin, p->chunk_len, p->chunk_slot,
-                    p->split_row, p->split_slot0, p->split_nslot};
+                    p->split_row, p->split_slot0, p->split_nslot, p->slot_chunk};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -221,6 +221,12 @@ int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **ou
     if (rc == ALS_OK) rc = upload(&p->split_row, srow);
     if (rc == ALS_OK) rc = upload(&p->split_slot0, sslot0);
     if (rc == ALS_OK) rc = upload(&p->split_nslot, snslot);
+    if (rc == ALS_OK) {
+        std::vector<int32_t> slot_chunk((size_t)slots, 0);
+        for (size_t k = 0; k < cslot2.size(); ++k)
+            if (cslot2[k] >= 0) slot_chunk[(size_t)cslot2[k]] = (int32_t)k;
+        rc = upload(&p->slot_chunk, slot_chunk);
+    }
     if (rc != ALS_OK) {
         als_plan_destroy(p);
         return rc;
@@ -241,6 +247,28 @@ int als_sweep(als_ctx *ctx, const als_plan *plan, const als_csr *R, const void *
     if (grad_out && (grad_out == X || grad_out == X_at || grad_out == Y)) return ALS_E_INVAL;
     return launch_sweep(ctx, plan, R, Y, X, n_f, ld, lambda, dt, X_at, grad_out, bad_row,
                         (hipStream_t)stream);
+}
+
+int als_sweep_mixed(als_ctx *ctx, const als_plan *plan, const als_csr *R, const void *Y16,
+                    const float *Y32, float *X32, void *X16, int n_f, int ld, double lambda,
+                    int refine, int64_t *bad_row, void *stream) {
+    if (!ctx || !csr_ok(R) || !plan_matches(plan, R) || !X32 || ld < n_f || n_f < 1 || n_f > 143 ||
+        !lambda_ok(lambda))
+        return ALS_E_INVAL;
+    if (R->nnz > 0 && (!Y16 || (refine && !Y32))) return ALS_E_INVAL;
+    if ((const void *)X32 == Y16 || X32 == Y32 ||
+        (X16 && (X16 == Y16 || X16 == (const void *)Y32 || X16 == (void *)X32)))
+        return ALS_E_INVAL;
+    if (plan->n_slots > 0 && !plan->slot_chunk) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_sweep_mixed(ctx, plan, R, Y16, Y32, X32, X16, n_f, ld, lambda, refine, bad_row,
+                              (hipStream_t)stream);
+}
+
+int als_to_bf16(als_ctx *ctx, int64_t n, const float *x, void *y, void *stream) {
+    if (!ctx || n < 0 || (n > 0 && (!x || !y))) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_to_bf16(n, x, y, (hipStream_t)stream);
 }
 
 int ncg_gradient(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, const als_plan *plan_Rt,

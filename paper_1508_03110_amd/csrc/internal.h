@@ -100,6 +100,9 @@ struct Plan {
     int32_t *split_row = nullptr;
     int32_t *split_slot0 = nullptr;
     int32_t *split_nslot = nullptr;
+    // split chunks: slot -> index of its chunk in chunk order (may be null
+    // for plans that are only used by the FP32/FP64 half-sweep)
+    int32_t *slot_chunk = nullptr;
 };
 
 struct Ctx {
@@ -132,6 +135,12 @@ int launch_fold_in(Ctx *ctx, const void *M, int n_f, int ld, double lambda, als_
 size_t sweep_partial_bytes(int n_f, als_dtype dt);
 int launch_sweep_batch(const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f, int ld,
                        double lambda, als_dtype dt, void *partial, int32_t *status, hipStream_t s);
+// Reduced-precision half-sweep (BF16 copies, BF16 MFMA Gram, FP32 solve,
+// optional refinement against the FP32 factors); planned only.
+int launch_sweep_mixed(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y16,
+                       const float *Y32, float *X32, void *X16, int n_f, int ld, double lambda,
+                       int refine, int64_t *bad_row, hipStream_t s);
+int launch_to_bf16(int64_t n, const float *x, void *y, hipStream_t s);
 int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
                     const void *U, const void *M, int n_f, int ld, double lambda, als_dtype dt,
                     void *gU, void *gM, double *out2, hipStream_t s);

@@ -27,23 +27,10 @@
 #include <climits>
 
 #include "internal.h"
+#include "rowsolve.h"
 
 namespace alsncg {
 namespace {
-
-template <int NB> struct Tri {
-    static constexpr int NT = NB * (NB + 1) / 2;
-    __host__ __device__ static constexpr int id(int a, int b) { return a * NB - a * (a - 1) / 2 + (b - a); }
-};
-
-// LDS per wavefront: two vectors of NB*16, one 16x17 transpose tile and the
-// NB inverted diagonal factors R_kk^{-T} (16x17 each, kept for the back
-// substitution).
-template <typename T, int NB> struct Shared {
-    static constexpr int NP = NB * 16;
-    static constexpr int TS = 16 * 17;
-    static constexpr int size = 2 * NP + TS + NB * TS;
-};
 
 // Slot order of the Gram matrix.  Slot s = 16 cb + c (tile block cb, lane
 // column c) holds factor column pi(s):
@@ -216,12 +203,7 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
         if (status && lane == 0) status[row] = empty_status;
         return;
     }
-    const T reg = lambda * (T)n_i;
-#pragma unroll
-    for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (MF::row(g, r) == c && 16 * a + c < n_f) A[TR::id(a, a)][r] += reg;
+    regularize<T, NB>(A, lambda * (T)n_i, n_f);
 
     const int caug = n_f - 16 * (NB - 1);  // lane column of the augmented column
 
@@ -273,111 +255,20 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
         __syncthreads();
     }
 
-    // ---- blocked Cholesky A = R^T R of the augmented matrix (pivots 0 .. n_f-1)
-    //
-    // Block row kb: the 16x16 diagonal tile is copied to LDS and factored
-    // together with an identity block, 32 columns = 32 lanes, each lane owning
-    // one column in 16 registers; row kk of the pivot block is broadcast with
-    // readlane.  Lanes 0..15 end with the columns of R_kk, lanes 16..31 with
-    // those of R_kk^{-T} (the forward substitution R_kk^T Y = I).  The other
-    // tiles of the block row are then R(kb, b) = R_kk^{-T} A(kb, b), 4 MFMAs
-    // each, and the trailing update A(a, b) -= R(kb, a)^T R(kb, b) 4 more.
+    // ---- blocked Cholesky A = R^T R of the augmented matrix (pivots 0 .. n_f-1);
+    // column n_f of the factor is then z with R^T z = v.
     T *Dt = sm + 2 * NP;
     T *Yinv = Dt + Shared<T, NB>::TS;
-    constexpr int TS = Shared<T, NB>::TS;
-    bool bad = false;
-#pragma unroll
-    for (int kb = 0; kb < NB; ++kb) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Dt[MF::row(g, r) * 17 + c] = A[TR::id(kb, kb)][r];
-        __syncthreads();
-        T p[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            p[i] = lane < 16 ? Dt[i * 17 + lane] : (i == (lane & 15) ? T(1) : T(0));
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            if (16 * kb + kk < n_f) {
-                T d = readlane(p[kk], kk);
-                if (!(d > T(0))) {
-                    bad = true;
-                    d = T(1);
-                }
-                p[kk] *= inv_sqrt(d);
-                T rk[16];  // row kk of the factor, broadcast first, then used
-#pragma unroll
-                for (int i = kk + 1; i < 16; ++i) rk[i] = readlane(p[kk], i);
-#pragma unroll
-                for (int i = kk + 1; i < 16; ++i) p[i] -= rk[i] * p[kk];
-            }
-        }
-        __syncthreads();
-        if (lane < 16) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) Dt[i * 17 + lane] = p[i];
-        } else if (lane < 32) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) Yinv[kb * TS + i * 17 + (lane - 16)] = p[i];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) A[TR::id(kb, kb)][r] = Dt[MF::row(g, r) * 17 + c];
-        if (kb + 1 < NB) {
-            T aop[4];
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) aop[s4] = Yinv[kb * TS + c * 17 + MF::row(g, s4)];
-#pragma unroll
-            for (int bb = kb + 1; bb < NB; ++bb) {
-                typename Mfma<T>::acc4 t = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) t = Mfma<T>::mma(aop[s4], A[TR::id(kb, bb)][s4], t);
-                A[TR::id(kb, bb)] = t;
-            }
-        }
-#pragma unroll
-        for (int a = kb + 1; a < NB; ++a)
-#pragma unroll
-            for (int bb = a; bb < NB; ++bb)
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4)
-                    A[TR::id(a, bb)] = Mfma<T>::mma(-A[TR::id(kb, a)][s4], A[TR::id(kb, bb)][s4],
-                                                    A[TR::id(a, bb)]);
-        __syncthreads();
-    }
+    const bool bad = cholesky_blocked<T, NB>(A, n_f, Dt, Yinv);
 
-    // ---- back substitution R x = z (z = column n_f of the factor), block by
-    // block from the last: z_kb -= R(kb, b) x_b for b > kb, x_kb = R_kk^{-1} z_kb
-    // = Y^T z_kb with the stored Y = R_kk^{-T}.
+    // ---- back substitution R x = z
     if (c == caug) {
 #pragma unroll
         for (int a = 0; a < NB; ++a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) ys[16 * a + MF::row(g, r)] = A[TR::id(a, NB - 1)][r];
     }
-    for (int k = lane; k < NP; k += kWave) xs[k] = T(0);
-    __syncthreads();
-#pragma unroll
-    for (int kb = NB - 1; kb >= 0; --kb) {
-        if (16 * kb < n_f) {
-            T part[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-            for (int bb = kb + 1; bb < NB; ++bb) {
-                const T xv = xs[16 * bb + c];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) part[r] += A[TR::id(kb, bb)][r] * xv;
-            }
-            T xp = T(0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = MF::row(g, r);
-                const T z = (16 * kb + i < n_f) ? ys[16 * kb + i] - sum16(part[r]) : T(0);
-                xp += Yinv[kb * TS + i * 17 + c] * z;
-            }
-            xp = sum4g(xp);
-            if (g == 0 && 16 * kb + c < n_f) xs[16 * kb + c] = xp;
-            __syncthreads();
-        }
-    }
+    back_solve<T, NB>(A, n_f, ys, xs, Yinv);
     for (int k = lane; k < n_f; k += kWave) xrow[Slots<NB>::col(k)] = bad ? T(NAN) : xs[k];
     if (lane == 0) {
         if (bad && bad_row) atomicMin((unsigned long long *)bad_row, (unsigned long long)row);

@@ -126,6 +126,19 @@ class DeviceProblem:
         L.als_sweep(self.ctx.handle, A.plan, A.csr, Y, X, self.n_f, self.ld, self.lam, self.dt,
                     X_at, grad_out, bad_row)
 
+    def sweep_mixed(self, side: str, Y16, Y32, X32, X16=None, refine: bool = True, bad_row=None):
+        """Reduced-precision half-sweep: Gram from the BF16 copy Y16, solve in
+        FP32, optional refinement against Y32 (FP32 factors only)."""
+        A = self.R if side == "U" else self.Rt
+        L.als_sweep_mixed(self.ctx.handle, A.plan, A.csr, Y16, Y32, X32, X16, self.n_f, self.ld,
+                          self.lam, refine, bad_row)
+
+    def bf16_rows(self, n_rows: int):
+        return torch.empty((n_rows, self.ld), dtype=torch.bfloat16, device=self.ctx.torch_device)
+
+    def to_bf16(self, X32, X16):
+        L.als_to_bf16(self.ctx.handle, X32.numel(), X32, X16)
+
     def gradient(self, U, M, gU=None, gM=None, out2=None):
         L.ncg_gradient(self.ctx.handle, self.R.plan, self.R.csr, self.Rt.plan, self.Rt.csr, U, M,
                        self.n_f, self.ld, self.lam, self.dt, gU, gM, out2)
@@ -143,18 +156,39 @@ class DeviceProblem:
         return f, math.sqrt(max(gg, 0.0))
 
 
-class Als:
-    """Algorithm 1: U half-sweep from M, then M half-sweep from the new U."""
+def _check_precision(prob: DeviceProblem, precision: str):
+    if precision not in ("fp", "bf16"):
+        raise ValueError("precision must be 'fp' (the factor type) or 'bf16'")
+    if precision == "bf16" and prob.dtype != torch.float32:
+        raise ValueError("the bf16 form keeps FP32 factors next to their BF16 copies")
 
-    def __init__(self, prob: DeviceProblem, x0=None):
+
+class Als:
+    """Algorithm 1: U half-sweep from M, then M half-sweep from the new U.
+
+    precision="bf16": the half-sweeps build their Gram matrices from BF16
+    copies of the fixed side (refined against the FP32 factors when
+    `refine`); the factors themselves stay FP32."""
+
+    def __init__(self, prob: DeviceProblem, x0=None, precision: str = "fp", refine: bool = True):
+        _check_precision(prob, precision)
         self.p = prob
         self.x = prob.zeros() if x0 is None else x0
         self.k = 0
+        self.precision, self.refine = precision, refine
+        if precision == "bf16":
+            self.u16 = prob.bf16_rows(prob.n_u)
+            self.m16 = prob.bf16_rows(prob.n_m)
+            prob.to_bf16(prob.M(self.x), self.m16)
 
     def sweep(self):
         P = self.p
-        P.sweep("U", P.M(self.x), P.U(self.x))
-        P.sweep("M", P.U(self.x), P.M(self.x))
+        if self.precision == "bf16":
+            P.sweep_mixed("U", self.m16, P.M(self.x), P.U(self.x), self.u16, self.refine)
+            P.sweep_mixed("M", self.u16, P.U(self.x), P.M(self.x), self.m16, self.refine)
+        else:
+            P.sweep("U", P.M(self.x), P.U(self.x))
+            P.sweep("M", P.U(self.x), P.M(self.x))
         self.k += 1
 
 
@@ -169,8 +203,13 @@ class AlsNcg:
 
     def __init__(self, prob: DeviceProblem, safeguard: bool = True, pr_plus: bool = False,
                  alpha0: float = ALPHA0, tau: float = TAU, c: float = C_ARMIJO,
-                 max_trials: int = MAX_TRIALS):
+                 max_trials: int = MAX_TRIALS, precision: str = "fp", refine: bool = True):
+        _check_precision(prob, precision)
         self.p = prob
+        self.precision, self.refine = precision, refine
+        if precision == "bf16":
+            self.u16 = prob.bf16_rows(prob.n_u)   # BF16 copy of U(P(x))
+            self.m16 = prob.bf16_rows(prob.n_m)   # BF16 copy of M(x)
         self.safeguard, self.pr_plus = safeguard, pr_plus
         self.alpha0, self.tau, self.c, self.max_trials = alpha0, tau, c, max_trials
         dev = prob.ctx.torch_device
@@ -218,6 +257,21 @@ class AlsNcg:
         """xbar = P(x) (two half-sweeps); g_new = grad f(x): the U block fused
         into the U half-sweep, the M block by one pass over R^T."""
         P = self.p
+        if self.precision == "bf16":
+            # the gradient cannot come from the BF16 Gram: both blocks by passes
+            t = self._mark("to_bf16")
+            P.to_bf16(P.M(self.x), self.m16)
+            self._done(t)
+            t = self._mark("sweep_U")
+            P.sweep_mixed("U", self.m16, P.M(self.x), P.U(self.xbar), self.u16, self.refine)
+            self._done(t)
+            t = self._mark("sweep_M")
+            P.sweep_mixed("M", self.u16, P.U(self.xbar), P.M(self.xbar), None, self.refine)
+            self._done(t)
+            t = self._mark("gradient")
+            P.gradient(P.U(self.x), P.M(self.x), P.U(self.g_new), P.M(self.g_new), None)
+            self._done(t)
+            return
         t = self._mark("sweep_U")
         P.sweep("U", P.M(self.x), P.U(self.xbar), X_at=P.U(self.x), grad_out=P.U(self.g_new))
         self._done(t)

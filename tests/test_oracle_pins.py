@@ -340,3 +340,63 @@ def test_als_ncg_decreases_f_and_q_matches_f(c0):
         f_prev = f_now
     _, _, fa = oracle.als_run(c0.R, c0.Rt, c0.M0, c0.lam, 1)
     assert f_prev < fa[0]
+
+
+# ---------------------------------------------------------------- reduced precision
+
+def test_bf16_round_matches_torch_and_hand_values():
+    """bf16_round against torch's float32 -> bfloat16 conversion (round to
+    nearest even, an independent implementation) on random magnitudes over 40
+    decades, and hand-rounded values: 1 + 2^-8 is a tie between 1 and
+    1 + 2^-7 and goes to the even mantissa (1); 1 + 3 2^-8 is a tie that goes
+    up to 1 + 2^-6 (1.015625); 65504 (the largest FP16) rounds to 65536."""
+    import torch
+    rng = np.random.default_rng(7)
+    x = (rng.standard_normal(200_000) * 10.0 ** rng.integers(-20, 20, 200_000)).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(oracle.bf16_round(x), ref)
+    hand = {1.0: 1.0, 1 + 2**-8: 1.0, 1 + 3 * 2**-8: 1.015625, 1 + 2**-8 + 2**-20: 1 + 2**-7,
+            -2.5: -2.5, 65504.0: 65536.0, 0.1: 0.10009765625}
+    got = oracle.bf16_round(np.array(list(hand), dtype=np.float32))
+    np.testing.assert_array_equal(got, np.array(list(hand.values())))
+
+
+def test_mixed_half_sweep_on_bf16_exact_inputs_is_the_plain_row_solve():
+    """With factors and ratings that bfloat16 represents exactly (8 significant
+    bits), rounding changes nothing and the unrefined reduced-precision solve
+    is the plain row solve of Eq. (3) computed by the C oracle; the refinement
+    step then adds a zero residual."""
+    P = small(seed=11, n_f=5)
+    M = oracle.bf16_round(P.M0.astype(np.float32)).reshape(P.M0.shape)
+    ref = oracle.half_sweep(P.R, M, P.lam)
+    assert rel(oracle.mixed_half_sweep(P.R, M, P.lam, refine=False), ref) < 1e-12
+    assert rel(oracle.mixed_half_sweep(P.R, M, P.lam, refine=True), ref) < 1e-12
+
+
+def test_mixed_refinement_error_identity():
+    """One refinement step obeys x1 - x* = (I - At^{-1} A)(x0 - x*), x* the
+    exact row solve (C oracle), A the FP32 normal matrix and At its bfloat16
+    counterpart: x1 = x0 + At^{-1}(v - A x0) and v = A x*.  A dropped term, a
+    sign or a transposed operand in the refinement breaks the identity; the
+    step must also shrink the error."""
+    P = small(seed=12, n_f=6, n_u=25)
+    M = P.M0.astype(np.float32)
+    xs = oracle.half_sweep(P.R, M.astype(np.float64), P.lam)
+    x0 = oracle.mixed_half_sweep(P.R, M, P.lam, refine=False)
+    x1 = oracle.mixed_half_sweep(P.R, M, P.lam, refine=True)
+    Mt = oracle.bf16_round(M).reshape(M.shape)
+    Md = M.astype(np.float64)
+    e0 = e1 = 0.0
+    for i in range(P.R.n_rows):
+        lo, hi = P.R.indptr[i], P.R.indptr[i + 1]
+        ids = P.R.indices[lo:hi]
+        if hi == lo:
+            continue
+        n = hi - lo
+        A = Md[ids].T @ Md[ids] + P.lam * n * np.eye(P.n_f)
+        At = Mt[ids].T @ Mt[ids] + P.lam * n * np.eye(P.n_f)
+        pred = (np.eye(P.n_f) - np.linalg.solve(At, A)) @ (x0[i] - xs[i])
+        np.testing.assert_allclose(x1[i] - xs[i], pred, rtol=0, atol=1e-10 * np.abs(xs[i]).max())
+        e0 = max(e0, np.abs(x0[i] - xs[i]).max())
+        e1 = max(e1, np.abs(x1[i] - xs[i]).max())
+    assert e0 > 1e-4 and e1 < 0.05 * e0
