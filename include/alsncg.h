@@ -253,6 +253,47 @@ ALS_API int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int l
             als_dtype dt, int64_t n_req, const int64_t *req_indptr, const int32_t *req_items,
             const float *req_vals, void *U_out, int32_t *req_status, void *stream);
 
+/* ---------------------------------------------------------------- device-side step control
+ *
+ * The two calls below run one step of Algorithm 2 with every decision taken
+ * on the device, so that a whole iteration is a fixed sequence of launches
+ * with no host read (it may be captured as one HIP graph).
+ */
+
+/*
+ * Line search and update of Algorithm 2 (Section V-C, Algorithm 4) with the
+ * restart and ALS-point safeguards, on the flat vectors x, p of Eq. (5)
+ * ([U; M] with U = x, M = x + R->n_rows * ld):
+ *   1. C = coefficients of f(x + alpha p) (one pass, as linesearch_coeffs);
+ *      alpha by backtracking (alpha0, tau, c, max_trials as ncg_backtrack);
+ *   2. if C1 >= 0 or no trial passed: p = -gbar and step 1 again (restart);
+ *   3. if that fails too: the ALS point x = x - gbar (= x + p) is taken
+ *      (safeguard; the next direction must restart), else x = x + alpha p.
+ * gbar: the preconditioned gradient x - P(x) (what ncg_direction leaves in
+ * its xbar argument).  state: device double[32], caller-owned, zeroed before
+ * the first step; after the call
+ *   state[16..20] accepted C0..C4, [21] step applied (alpha, or 1 for the ALS
+ *   point), [22] trials (-1 after a safeguard), [23] 1 if p was restarted,
+ *   [24] 1 if the ALS point was taken, [25] f(x_new) = Q(alpha) (NaN after a
+ *   safeguard), [26] restarts so far, [27] safeguards so far, [28] steps so far;
+ *   [0..15] hold the two coefficient sets and trial results.
+ * The second coefficient pass is launched in every case and returns at once
+ * unless the restart flag is set.  Errors as linesearch_coeffs.
+ */
+ALS_API int ncg_linesearch_step(als_ctx *ctx, const als_plan *plan_R, const als_csr *R,
+                                const als_csr *Rt, void *x, void *p, const void *gbar, int n_f,
+                                int ld, double lambda, als_dtype dt, double alpha0, double tau,
+                                double c, int max_trials, double *state, void *stream);
+
+/*
+ * ncg_direction with the restart decided on the device: beta = 0 when
+ * *restart_flag != 0 (device double, e.g. state + 24 of ncg_linesearch_step),
+ * else Eq. (8).  g_old must be valid.  Same outputs as ncg_direction.
+ */
+ALS_API int ncg_direction_dev(als_ctx *ctx, int64_t n, const void *x, void *xbar,
+                              const void *g_new, const void *g_old, void *p, double *scal,
+                              const double *restart_flag, int pr_plus, als_dtype dt, void *stream);
+
 /* ---------------------------------------------------------------- serving
  *
  * Fold-in server: new users (requests) are solved against fixed item factors

@@ -293,7 +293,7 @@ int linesearch_coeffs(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, co
         return ALS_E_INVAL;
     if (Rt->n_rows != R->n_cols) return ALS_E_INVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
-    return launch_coeffs(ctx, plan_R, R, Rt, U, M, pU, pM, n_f, ld, lambda, dt, coeffs,
+    return launch_coeffs(ctx, plan_R, R, Rt, U, M, pU, pM, n_f, ld, lambda, dt, coeffs, nullptr,
                          (hipStream_t)stream);
 }
 
@@ -330,8 +330,47 @@ int ncg_direction(als_ctx *ctx, int64_t n, const void *x, void *xbar, const void
     if (n > 0 && (!x || !xbar || !g_new || !p || (!restart && !g_old))) return ALS_E_INVAL;
     if (dt != ALS_F32 && dt != ALS_F64) return ALS_E_INVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
-    return launch_direction(ctx, n, x, xbar, g_new, g_old, p, scal, restart, pr_plus, dt,
+    return launch_direction(ctx, n, x, xbar, g_new, g_old, p, scal, restart, nullptr, pr_plus, dt,
                             (hipStream_t)stream);
+}
+
+int ncg_direction_dev(als_ctx *ctx, int64_t n, const void *x, void *xbar, const void *g_new,
+                      const void *g_old, void *p, double *scal, const double *restart_flag,
+                      int pr_plus, als_dtype dt, void *stream) {
+    if (!ctx || n < 0 || !scal || !restart_flag) return ALS_E_INVAL;
+    if (n > 0 && (!x || !xbar || !g_new || !g_old || !p)) return ALS_E_INVAL;
+    if (dt != ALS_F32 && dt != ALS_F64) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_direction(ctx, n, x, xbar, g_new, g_old, p, scal, 0, restart_flag, pr_plus, dt,
+                            (hipStream_t)stream);
+}
+
+int ncg_linesearch_step(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, const als_csr *Rt,
+                        void *x, void *p, const void *gbar, int n_f, int ld, double lambda,
+                        als_dtype dt, double alpha0, double tau, double c, int max_trials,
+                        double *state, void *stream) {
+    if (!ctx || !csr_ok(R) || !Rt || !Rt->indptr || !plan_matches(plan_R, R) || !x || !p ||
+        !gbar || !state || ld < n_f || !lambda_ok(lambda) || !dtype_ok(dt, n_f, false))
+        return ALS_E_INVAL;
+    if (Rt->n_rows != R->n_cols || !(alpha0 > 0.0) || !(tau > 0.0 && tau < 1.0) ||
+        !(c > 0.0 && c < 1.0) || max_trials < 1)
+        return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t elt = dt == ALS_F64 ? sizeof(double) : sizeof(float);
+    const int64_t n_u = R->n_rows, n = (R->n_rows + R->n_cols) * (int64_t)ld;
+    char *xU = (char *)x, *pU = (char *)p;
+    char *xM = xU + (size_t)n_u * ld * elt, *pM = pU + (size_t)n_u * ld * elt;
+    int rc = launch_coeffs(ctx, plan_R, R, Rt, xU, xM, pU, pM, n_f, ld, lambda, dt, state,
+                           nullptr, s);
+    if (rc == ALS_OK) rc = launch_ls_first(state, alpha0, tau, c, max_trials, s);
+    if (rc == ALS_OK) rc = launch_ls_restart_dir(n, p, gbar, state, dt, s);
+    if (rc == ALS_OK)
+        rc = launch_coeffs(ctx, plan_R, R, Rt, xU, xM, pU, pM, n_f, ld, lambda, dt, state + 8,
+                           state + 7, s);
+    if (rc == ALS_OK) rc = launch_ls_final(state, alpha0, tau, c, max_trials, s);
+    if (rc == ALS_OK) rc = launch_axpy(n, x, p, state + 21, dt, s);
+    return rc;
 }
 
 int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int ld, double lambda,

@@ -146,7 +146,7 @@ int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt,
                     void *gU, void *gM, double *out2, hipStream_t s);
 int launch_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const void *U,
                   const void *M, const void *pU, const void *pM, int n_f, int ld, double lambda,
-                  als_dtype dt, double *coeffs, hipStream_t s);
+                  als_dtype dt, double *coeffs, const double *pred, hipStream_t s);
 int launch_backtrack(const double *coeffs, double alpha0, double tau, double c, int max_trials,
                      double *alpha_out, int32_t *trials_out, hipStream_t s);
 int launch_axpy(int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,
@@ -154,8 +154,17 @@ int launch_axpy(int64_t n, void *x, const void *p, const double *alpha, als_dtyp
 int launch_axpby(int64_t n, double a, const void *x, double b, void *y, als_dtype dt,
                  hipStream_t s);
 int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void *g_new,
-                     const void *g_old, void *p, double *scal, int restart, int pr_plus,
-                     als_dtype dt, hipStream_t s);
+                     const void *g_old, void *p, double *scal, int restart,
+                     const double *restart_dev, int pr_plus, als_dtype dt, hipStream_t s);
+// Device-side line-search control (Algorithm 4 with the safeguards), see
+// ncg_linesearch_step in the header for the state layout.
+constexpr int kLsState = 32;
+int launch_ls_first(double *state, double alpha0, double tau, double c, int max_trials,
+                    hipStream_t s);
+int launch_ls_restart_dir(int64_t n, void *p, const void *gbar, const double *state, als_dtype dt,
+                          hipStream_t s);
+int launch_ls_final(double *state, double alpha0, double tau, double c, int max_trials,
+                    hipStream_t s);
 
 // Deterministic FP64 column sums of a row-major [rows, cols] array, cols <= 8
 // (two launches, fixed order).  out[k] = sum_r parts[r * cols + k] (+ out[k]

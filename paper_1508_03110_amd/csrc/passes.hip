@@ -215,10 +215,10 @@ __global__ __launch_bounds__(64) void coeff_chunks_kernel(
     const T *__restrict__ PU, const T *__restrict__ PM, int n_f, int ld, double lambda,
     int64_t n_chunks, const int32_t *__restrict__ chunk_row,
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
-    double *__restrict__ part) {
+    double *__restrict__ part, const double *__restrict__ pred) {
     typedef typename Vec<T, VEC>::type V;
     const int64_t q = blockIdx.x;
-    if (q >= n_chunks) return;
+    if (q >= n_chunks || (pred && *pred == 0.0)) return;
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     const int64_t row = chunk_row[q], b = chunk_begin[q], e = b + chunk_len[q];
     V xu[NV], pu[NV];
@@ -314,8 +314,10 @@ __global__ __launch_bounds__(256) void coeff_itemreg_kernel(const int64_t *__res
                                                             const T *__restrict__ XM,
                                                             const T *__restrict__ PM, int n_f,
                                                             int ld, double lambda,
-                                                            double *__restrict__ part) {
+                                                            double *__restrict__ part,
+                                                            const double *__restrict__ pred) {
     __shared__ double red[4][3];
+    if (pred && *pred == 0.0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
     double xx = 0.0, xp = 0.0, pp = 0.0;
     for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * 4; base < n_items;
@@ -424,7 +426,7 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
 template <typename T, int VEC, int NV>
 int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const T *U,
                const T *M, const T *PU, const T *PM, int n_f, int ld, double lambda,
-               double *coeffs, hipStream_t s) {
+               double *coeffs, const double *pred, hipStream_t s) {
     const int64_t rows = pR->n_chunks + kItemBlocks;
     int err = ALS_OK;
     double *part =
@@ -434,9 +436,10 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
         hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV>), dim3((unsigned)pR->n_chunks),
                            dim3(kWave), 0, s, R->indptr, R->indices, R->values, U, M, PU, PM, n_f,
                            ld, lambda, pR->n_chunks, pR->chunk_row, pR->chunk_begin,
-                           pR->chunk_len, part);
+                           pR->chunk_len, part, pred);
     hipLaunchKernelGGL((coeff_itemreg_kernel<T, NV * VEC>), dim3(kItemBlocks), dim3(256), 0, s,
-                       Rt->indptr, Rt->n_rows, M, PM, n_f, ld, lambda, part + 5 * pR->n_chunks);
+                       Rt->indptr, Rt->n_rows, M, PM, n_f, ld, lambda, part + 5 * pR->n_chunks,
+                       pred);
     launch_sum_columns(part, rows, 5, coeffs, 0, part + rows * 5, s);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
@@ -492,9 +495,9 @@ int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt,
 
 int launch_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const void *U,
                   const void *M, const void *pU, const void *pM, int n_f, int ld, double lambda,
-                  als_dtype dt, double *coeffs, hipStream_t s) {
+                  als_dtype dt, double *coeffs, const double *pred, hipStream_t s) {
 #define CA(T, VEC, NV) \
-    return run_coeffs<T, VEC, NV>(ctx, pR, R, Rt, (const T *)U, (const T *)M, (const T *)pU, (const T *)pM, n_f, ld, lambda, coeffs, s)
+    return run_coeffs<T, VEC, NV>(ctx, pR, R, Rt, (const T *)U, (const T *)M, (const T *)pU, (const T *)pM, n_f, ld, lambda, coeffs, pred, s)
     if (dt == ALS_F32 && vec4_ok(n_f, ld, {U, M, pU, pM})) {
         switch ((n_f + 63) / 64) {
             case 1: CA(float, 4, 1);

@@ -135,9 +135,11 @@ __global__ __launch_bounds__(kVecThreads) void direction_dots_kernel(
 // scal[0] = den (in: gbar_k.g_k, out: gbar_{k+1}.g_{k+1}); scal[1] = beta;
 // scal[2] = ||g||^2; scal[3] = numerator of Eq. (8).
 __global__ void direction_beta_kernel(const double *__restrict__ sums, double *__restrict__ scal,
-                                      int restart, int pr_plus) {
+                                      int restart, const double *__restrict__ restart_dev,
+                                      int pr_plus) {
     const double num = sums[0], den_new = sums[1], gg = sums[2];
     const double den = scal[0];
+    if (restart_dev && *restart_dev != 0.0) restart = 1;
     double beta = 0.0;
     if (!restart && den != 0.0 && isfinite(den)) beta = num / den;
     if (!isfinite(beta)) beta = 0.0;
@@ -159,9 +161,10 @@ __global__ __launch_bounds__(kVecThreads) void direction_update_kernel(
 
 // ---------------------------------------------------------------- backtracking
 
-__global__ void backtrack_kernel(const double *__restrict__ C, double alpha0, double tau, double c,
-                                 int max_trials, double *__restrict__ alpha_out,
-                                 int32_t *__restrict__ trials_out) {
+// First alpha = alpha0 tau^n (n < max_trials) passing the divided Armijo
+// test; alpha = 0, n = -1 when none passes or C1 >= 0.
+__device__ void backtrack_search(const double *C, double alpha0, double tau, double c,
+                                 int max_trials, double *alpha_out, int *n_out) {
     // no FMA contraction: the accept/reject decision must be taken with the
     // same roundings as a plain evaluation of the test
 #pragma clang fp contract(off)
@@ -180,7 +183,73 @@ __global__ void backtrack_kernel(const double *__restrict__ C, double alpha0, do
         }
     }
     *alpha_out = acc;
+    *n_out = n;
+}
+
+__global__ void backtrack_kernel(const double *__restrict__ C, double alpha0, double tau, double c,
+                                 int max_trials, double *__restrict__ alpha_out,
+                                 int32_t *__restrict__ trials_out) {
+    double a;
+    int n;
+    backtrack_search(C, alpha0, tau, c, max_trials, &a, &n);
+    *alpha_out = a;
     if (trials_out) *trials_out = n;
+}
+
+// ---------------------------------------------------------------- device-side step control
+//
+// state (double[32]): [0..4] C of the first direction, [5] its alpha, [6] its
+// trial count, [7] restart flag; [8..12], [13], [14] the same for the restarted
+// direction -gbar; [16..20] accepted C, [21] step applied (alpha, or 1 for the
+// ALS point), [22] trials (-1: safeguard), [23] restarted, [24] safeguarded,
+// [25] f(x_{k+1}) = Q(alpha) (NaN after a safeguard step), [26] total
+// restarts, [27] total safeguards, [28] iterations.
+
+__global__ void ls_first_kernel(double *__restrict__ st, double alpha0, double tau, double c,
+                                int max_trials) {
+    double a;
+    int n;
+    backtrack_search(st, alpha0, tau, c, max_trials, &a, &n);
+    st[5] = a;
+    st[6] = (double)n;
+    st[7] = (st[1] >= 0.0 || n < 0) ? 1.0 : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void ls_restart_dir_kernel(int64_t n, T *__restrict__ p,
+                                                                     const T *__restrict__ gbar,
+                                                                     const double *__restrict__ st) {
+    if (st[7] == 0.0) return;
+    for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kVecThreads)
+        p[i] = (T)(-(double)gbar[i]);
+}
+
+__global__ void ls_final_kernel(double *__restrict__ st, double alpha0, double tau, double c,
+                                int max_trials) {
+#pragma clang fp contract(off)
+    const bool restarted = st[7] != 0.0;
+    const double *C = st;
+    double alpha = st[5];
+    int n = (int)st[6];
+    bool safe = false;
+    if (restarted) {
+        backtrack_search(st + 8, alpha0, tau, c, max_trials, &alpha, &n);
+        st[13] = alpha;
+        st[14] = (double)n;
+        C = st + 8;
+        safe = C[1] >= 0.0 || n < 0;
+    }
+    for (int k = 0; k < 5; ++k) st[16 + k] = C[k];
+    st[21] = safe ? 1.0 : alpha;
+    st[22] = safe ? -1.0 : (double)n;
+    st[23] = restarted ? 1.0 : 0.0;
+    st[24] = safe ? 1.0 : 0.0;
+    // Q(alpha) by Horner from the highest coefficient
+    st[25] = safe ? NAN : (((C[4] * alpha + C[3]) * alpha + C[2]) * alpha + C[1]) * alpha + C[0];
+    st[26] += restarted ? 1.0 : 0.0;
+    st[27] += safe ? 1.0 : 0.0;
+    st[28] += 1.0;
 }
 
 }  // namespace
@@ -233,9 +302,35 @@ int launch_axpby(int64_t n, double a, const void *x, double b, void *y, als_dtyp
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
+int launch_ls_first(double *state, double alpha0, double tau, double c, int max_trials,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(ls_first_kernel, dim3(1), dim3(1), 0, s, state, alpha0, tau, c, max_trials);
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
+int launch_ls_final(double *state, double alpha0, double tau, double c, int max_trials,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(ls_final_kernel, dim3(1), dim3(1), 0, s, state, alpha0, tau, c, max_trials);
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
+int launch_ls_restart_dir(int64_t n, void *p, const void *gbar, const double *state, als_dtype dt,
+                          hipStream_t s) {
+    if (n == 0) return ALS_OK;
+    if (dt == ALS_F32)
+        hipLaunchKernelGGL(ls_restart_dir_kernel<float>, dim3(vec_grid(n)), dim3(kVecThreads), 0, s,
+                           n, (float *)p, (const float *)gbar, state);
+    else if (dt == ALS_F64)
+        hipLaunchKernelGGL(ls_restart_dir_kernel<double>, dim3(vec_grid(n)), dim3(kVecThreads), 0, s,
+                           n, (double *)p, (const double *)gbar, state);
+    else
+        return ALS_E_INVAL;
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
 int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void *g_new,
-                     const void *g_old, void *p, double *scal, int restart, int pr_plus,
-                     als_dtype dt, hipStream_t s) {
+                     const void *g_old, void *p, double *scal, int restart,
+                     const double *restart_dev, int pr_plus, als_dtype dt, hipStream_t s) {
     int err = ALS_OK;
     double *part = (double *)ctx->workspace(
         (size_t)(kVecBlocks * 3 + 8 + kSumStageDoubles) * sizeof(double), s, &err);
@@ -255,7 +350,8 @@ int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void 
     else
         return ALS_E_INVAL;
     launch_sum_columns(part, kVecBlocks, 3, sums, 0, stage, s);
-    hipLaunchKernelGGL(direction_beta_kernel, dim3(1), dim3(1), 0, s, sums, scal, restart, pr_plus);
+    hipLaunchKernelGGL(direction_beta_kernel, dim3(1), dim3(1), 0, s, sums, scal, restart,
+                       restart_dev, pr_plus);
     if (dt == ALS_F32)
         hipLaunchKernelGGL(direction_update_kernel<float>, dim3(vec_grid(n)), dim3(kVecThreads), 0,
                            s, n, (const float *)xbar, (float *)p, scal);

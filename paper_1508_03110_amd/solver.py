@@ -227,6 +227,9 @@ class AlsNcg:
         self.n_trials = 0
         self.coef = None
         self.timers = None  # {phase: [(start, end) torch.cuda.Event pairs]} when timing
+        # device-side step control (ncg_linesearch_step): decisions in `state`
+        self.state = torch.zeros(32, dtype=torch.float64, device=dev)
+        self.graphs = None
 
     def enable_timing(self, on: bool = True):
         """Record HIP events (on torch's current stream, where the library
@@ -334,6 +337,64 @@ class AlsNcg:
         self.coef, self.n_trials = C, n
         self._precondition_and_gradient()
         self._direction(restart=restart)
+        self.k += 1
+        return self
+
+    # -- Algorithm 2 with every decision on the device (no host read per step)
+    def step_device(self):
+        """One iteration as a fixed launch sequence: device-side line search,
+        restart and safeguard (same decisions as step()), preconditioner,
+        gradient, direction.  Host-visible results via read_state()."""
+        if not self.safeguard:
+            raise ValueError("device-side control implements the safeguarded iteration")
+        P = self.p
+        t = self._mark("linesearch")
+        L.ncg_linesearch_step(P.ctx.handle, P.R.plan, P.R.csr, P.Rt.csr, self.x, self.pdir,
+                              self.xbar, P.n_f, P.ld, P.lam, P.dt, self.alpha0, self.tau, self.c,
+                              self.max_trials, self.state)
+        self._done(t)
+        self._precondition_and_gradient()
+        t = self._mark("direction")
+        L.ncg_direction_dev(P.ctx.handle, P.N, self.x, self.xbar, self.g_new, self.g_old, self.pdir,
+                            self.scal, self.state[24:25], 1 if self.pr_plus else 0, P.dt)
+        self._done(t)
+        self.g_new, self.g_old = self.g_old, self.g_new
+        self.k += 1
+        return self
+
+    def read_state(self):
+        """Copy the device step state to the host attributes (synchronises)."""
+        st = self.state.cpu().numpy()
+        self.coef = st[16:21].copy()
+        self.alpha = float(st[21]) if st[24] == 0 else float("nan")
+        self.n_trials = int(st[22])
+        self.f = float(st[25])
+        self.restarts, self.safeguards = int(st[26]), int(st[27])
+        return self
+
+    def capture(self):
+        """Capture one device-controlled iteration as a HIP graph, twice: the
+        gradient buffers alternate between iterations, so graph k % 2 runs
+        iteration k.  The workspace must already have its final size (run one
+        step_device() first)."""
+        timers, self.timers = self.timers, None
+        graphs = []
+        for _ in range(2):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                self.step_device()
+            graphs.append(g)
+        self.k -= 2
+        self.timers = timers
+        self.graphs = graphs
+        self._graph_base = self.k
+        return self
+
+    def replay(self):
+        """Run the next iteration from the captured graphs (the buffers the
+        graphs were captured with; do not re-init after capturing)."""
+        self.graphs[(self.k - self._graph_base) % 2].replay()
+        self.g_new, self.g_old = self.g_old, self.g_new
         self.k += 1
         return self
 

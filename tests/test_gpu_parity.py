@@ -370,3 +370,58 @@ def test_als_ncg_20_iterations_lockstep(ctx, c0, dtype, tol):
     assert gpu.safeguards == 0 and flips <= 2
     _, _, fa = oracle.als_run(c0.R, c0.Rt, M0, c0.lam, 20)
     assert gpu.f < fa[-1]  # ALS-NCG ahead of ALS after the same number of iterations
+
+
+# ---------------------------------------------------------------- device-side control, graphs
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_device_controlled_step_matches_host_step(ctx, dtype):
+    """step_device() takes every line-search, restart and safeguard decision
+    on the device; from the same start it must reproduce step() bit for bit
+    (same kernels, same inputs), including forced restarts and ALS-point
+    steps: with alpha0 = 1e3 and 60 trials the search fails on some
+    iterations."""
+    from paper_1508_03110_amd.solver import AlsNcg
+    P = synth.random_problem(80, 60, n_f=6, lam=0.05, seed=21, density=0.25, x0_sigma=0.5)
+    DP = dev_problem(ctx, P, dtype)
+    U0 = P.U0 if dtype == torch.float64 else r32(P.U0)
+    M0 = P.M0 if dtype == torch.float64 else r32(P.M0)
+    for kw in ({}, dict(alpha0=1e3, max_trials=60)):
+        a = AlsNcg(DP, **kw).init(U0, M0)
+        b = AlsNcg(DP, **kw).init(U0, M0)
+        for k in range(12):
+            a.step()
+            b.step_device()
+            b.read_state()
+            assert torch.equal(a.x, b.x), (kw, k)
+            assert torch.equal(a.pdir, b.pdir), (kw, k)
+            assert (a.restarts, a.safeguards) == (b.restarts, b.safeguards), (kw, k)
+            if math.isnan(a.f):
+                assert math.isnan(b.f)
+            else:
+                assert a.f == b.f and a.n_trials == b.n_trials, (kw, k)
+        if kw:  # the FP64 oracle takes 7 restarts and 7 ALS points here
+            assert b.restarts > 0 and 0 < b.safeguards < 12
+
+
+def test_graph_replays_match_eager(ctx, c0):
+    """One ALS-NCG iteration captured as a HIP graph (two graphs, alternating
+    gradient buffers): six replays with eager work and synchronisations in
+    between, each compared bit for bit with an eager device-controlled run."""
+    from paper_1508_03110_amd.solver import AlsNcg
+    DP = dev_problem(ctx, c0, torch.float32, chunk=64, chunk_t=64)
+    U0, M0 = r32(c0.U0), r32(c0.M0)
+    ref = AlsNcg(DP).init(U0, M0)
+    g = AlsNcg(DP).init(U0, M0)
+    ref.step_device()
+    g.step_device()
+    g.capture()
+    for k in range(6):
+        ref.step_device()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device=ctx.torch_device).sum().item()  # eager work between replays
+        assert torch.equal(ref.x, g.x), k
+        assert torch.equal(ref.pdir, g.pdir), k
+        assert torch.equal(ref.state, g.state), k
+        assert torch.equal(ref.scal, g.scal), k
