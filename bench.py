@@ -272,6 +272,75 @@ def c3_bench(ctx, steps=20, gtol=1e-6, max_iter=400):
     return out
 
 
+def c2_bench(ctx, steps=5, als_steps=3):
+    """Billion-rating configuration: 10M users x 1M items, exactly 1e9 ratings
+    (power-law user activity on [1, 50000], Zipf 1.1 items), n_f = 50,
+    lambda = 0.05, generated on the device.  Plans tuned per orientation; ALS
+    sweeps timed eagerly; ALS-NCG timed as replays of the captured one-iteration
+    HIP graphs (device-side line-search control)."""
+    import numpy as np
+    import torch
+
+    from paper_1508_03110_amd import tune
+    from paper_1508_03110_amd.solver import Als, AlsNcg, DeviceCsr, DeviceProblem
+    from synth import scale
+    t0 = time.perf_counter()
+    R, U0, M0 = scale.generate(device=ctx.torch_device, log=lambda m: log("C2 gen: " + m))
+    n_f, lam = 50, 0.05
+    Rd = DeviceCsr(ctx, R.indptr, R.indices, R.values, R.n_m)
+    Rtd = DeviceCsr(ctx, R.indptr_t, R.indices_t, R.values_t, R.n_u)
+    meta = dict(R.meta)
+    del R
+    DP = DeviceProblem(ctx, Rd, Rtd, n_f, lam, torch.float32)
+    x0 = DP.pack(U0, M0)
+    del U0, M0
+    out = {"workload": "10M x 1M, 1e9 ratings, n_f=50", "n_u": DP.n_u, "n_m": DP.n_m,
+           "nnz": DP.R.nnz, "n_f": n_f, "lambda": lam, "generator": meta,
+           "setup_seconds": round(time.perf_counter() - t0, 1)}
+    log("C2 problem on device (%.1f s); plans R %s R^T %s" % (time.perf_counter() - t0, DP.R.info(), DP.Rt.info()))
+    out["tuning"] = tune.tune(DP, x0, log=log)
+    out["plans"] = {"R": DP.R.info(), "Rt": DP.Rt.info()}
+    # ALS (Algorithm 1), eager
+    als = Als(DP, x0.clone())
+    als.sweep()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(als_steps):
+        als.sweep()
+    torch.cuda.synchronize()
+    ms_als = (time.perf_counter() - t) / als_steps * 1e3
+    out["als"] = {"ms_per_sweep": ms_als, "ratings_per_s": 2.0 * DP.R.nnz / (ms_als * 1e-3)}
+    del als
+    torch.cuda.empty_cache()
+    # ALS-NCG: one eager device-controlled step with phase events, then graphs
+    s = AlsNcg(DP).init(x0[: DP.n_u * DP.ld].view(DP.n_u, DP.ld)[:, :n_f],
+                        x0[DP.n_u * DP.ld:].view(DP.n_m, DP.ld)[:, :n_f])
+    del x0
+    s.enable_timing(True)
+    s.step_device()
+    phases = s.phase_ms()
+    s.enable_timing(False)
+    s.capture()
+    s.replay()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        s.replay()
+    torch.cuda.synchronize()
+    ms_ncg = (time.perf_counter() - t) / steps * 1e3
+    s.read_state()
+    out["als_ncg"] = {"ms_per_iteration": ms_ncg, "ratings_per_s": 2.0 * DP.R.nnz / (ms_ncg * 1e-3),
+                      "graph_replays": steps, "phase_ms_eager_step": {k: round(v, 3) for k, v in phases.items()},
+                      "f": s.f, "gnorm_over_N": s.gnorm() / (n_f * (DP.n_u + DP.n_m)),
+                      "restarts": s.restarts, "safeguards": s.safeguards, "iterations": s.k}
+    fU = sweep_flops(DP.R.nnz, DP.n_u, n_f)
+    out["sweep_U_tflops_eager"] = fU / (phases["sweep_U"] * 1e-3) / 1e12
+    log("C2:", out["als"], out["als_ncg"])
+    del s, DP, Rd, Rtd
+    torch.cuda.empty_cache()
+    return out
+
+
 def serve_bench(ctx, M_dev, P, rates=(10_000, 50_000, 200_000), duration=2.0, warm=0.5,
                 baseline_cap=20_000, seed=4):
     """Fold-in serving: open-loop Poisson arrivals replayed in real time by the
@@ -322,6 +391,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the fold-in serving measurement")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-f-tolerance measurement")
     ap.add_argument("--no-c3", action="store_true", help="skip the reduced-precision measurement")
+    ap.add_argument("--no-c2", action="store_true", help="skip the billion-rating measurement")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM traffic counters)")
@@ -426,6 +496,11 @@ def main():
         del solver, DP
         torch.cuda.empty_cache()
         result["reduced_precision"] = c3_bench(ctx)
+    if not args.no_c2:
+        if args.no_c3:
+            del solver, DP
+            torch.cuda.empty_cache()
+        result["scale_1e9"] = c2_bench(ctx)
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

@@ -99,13 +99,21 @@ ALS_API size_t als_ctx_workspace_bytes(const als_ctx *ctx);
  * Section V-B): rows are cut into chunks of at most `chunk` ratings, chunks
  * are ordered longest first, and rows longer than `chunk` are marked for a
  * split-K second stage with a fixed-order reduction (results do not depend
- * on scheduling).  chunk = 0 picks a size from the matrix shape.  The call
+ * on scheduling).  chunk = 0 picks a size from the matrix shape:
+ * nnz / (8 x compute units), at least 256 and at most 8192 ratings (bounding
+ * the length of each FP32 MFMA accumulation; longer rows are split).  The call
  * copies R->indptr to the host (it synchronises the device) and allocates
  * the plan's device arrays; the plan stays valid until als_plan_destroy and
  * may only be used with a CSR of the same indptr.
  */
 ALS_API int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **out);
 ALS_API void als_plan_destroy(als_plan *plan);
+/* Launch shape of the chunk kernels that use this plan (half-sweep,
+ * gradient and coefficient passes): grid = 0 (default) launches one 64-lane
+ * workgroup per chunk; grid > 0 launches min(grid, chunks) persistent
+ * workgroups that stride over the chunks (longest first).  Results do not
+ * depend on it (every chunk writes its own partials).  Used by the tuner. */
+ALS_API int als_plan_set_grid(als_plan *plan, int64_t grid);
 /* Plan statistics: out[0]=n_rows, [1]=nnz, [2]=n_chunks, [3]=split rows,
  * [4]=split chunks, [5]=chunk size, [6]=longest row. */
 ALS_API int als_plan_info(const als_plan *plan, int64_t out[7]);

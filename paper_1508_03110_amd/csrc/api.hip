@@ -125,6 +125,12 @@ void als_plan_destroy(als_plan *p) {
     delete p;
 }
 
+int als_plan_set_grid(als_plan *p, int64_t grid) {
+    if (!p || grid < 0 || grid > INT32_MAX) return ALS_E_INVAL;
+    p->grid = grid;
+    return ALS_OK;
+}
+
 int als_plan_info(const als_plan *p, int64_t out[7]) {
     if (!p || !out) return ALS_E_INVAL;
     out[0] = p->n_rows;
@@ -136,6 +142,9 @@ int als_plan_info(const als_plan *p, int64_t out[7]) {
     out[6] = p->max_row;
     return ALS_OK;
 }
+
+// Longest chunk the automatic plan uses (ratings per wavefront).
+static constexpr int64_t kMaxAutoChunk = 8192;
 
 int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **out) {
     if (!out) return ALS_E_INVAL;
@@ -156,9 +165,14 @@ int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **ou
     }
     if (chunk == 0) {
         // at most the average work of one resident wavefront slot (8 per CU):
-        // longer rows are split so that no single wave dominates the launch
+        // longer rows are split so that no single wave dominates the launch.
+        // Capped at kMaxAutoChunk: an FP32 MFMA accumulator then sums at most
+        // kMaxAutoChunk / 4 steps; longer rows are reduced by the fixed-order
+        // second stage (VALU adds, rounded to nearest), which keeps the Gram
+        // of rows with millions of ratings accurate.
         const int64_t slots = (int64_t)ctx->num_cu * 8;
         chunk = std::max<int64_t>(256, (R->nnz + slots - 1) / slots);
+        chunk = std::min<int64_t>(chunk, kMaxAutoChunk);
         chunk = (chunk + 3) / 4 * 4;
     }
     chunk = std::min<int64_t>(chunk, INT32_MAX / 2);

@@ -13,6 +13,8 @@
 // order, so results are bitwise reproducible.
 #include <initializer_list>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace alsncg {
@@ -82,7 +84,7 @@ __device__ __forceinline__ void store_row(const typename Vec<T, VEC>::type (&v)[
 // that are whole in this chunk); split rows leave the regulariser and ||G||^2
 // to grad_split_kernel.  Rating ids are fetched two groups ahead and factor
 // rows one group ahead of their use.
-template <typename T, int VEC, int NV>
+template <typename T, int VEC, int NV, bool PERSIST>
 __global__ __launch_bounds__(64) void grad_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ X, const T *__restrict__ Y, int n_f,
@@ -91,8 +93,8 @@ __global__ __launch_bounds__(64) void grad_chunks_kernel(
     const int32_t *__restrict__ chunk_slot, T *__restrict__ G, T *__restrict__ partial,
     double *__restrict__ scal, int data_in_f, int want_g) {
     typedef typename Vec<T, VEC>::type V;
-    const int64_t q = blockIdx.x;
-    if (q >= n_chunks) return;
+    const int64_t stride = PERSIST ? (int64_t)gridDim.x : n_chunks;
+    for (int64_t q = blockIdx.x; q < n_chunks; q += stride) {
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     const int64_t row = chunk_row[q], b = chunk_begin[q], e = b + chunk_len[q];
     const int slot = chunk_slot[q];
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(64) void grad_chunks_kernel(
             scal[2 * q + 1] = 0.0;
         }
     }
+    }
 }
 
 template <typename T, int NP>
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(64) void grad_split_kernel(
 //   (r - u.m)^2 = d^2 - 2 d a1 alpha + (a1^2 - 2 d a2) alpha^2 + 2 a1 a2 alpha^3 + a2^2 alpha^4.
 // The first chunk of each user row also adds that user's regulariser
 // lambda n_i ||xu + alpha pu||^2.  part[5q + n] is the chunk's share of C_n.
-template <typename T, int VEC, int NV>
+template <typename T, int VEC, int NV, bool PERSIST>
 __global__ __launch_bounds__(64) void coeff_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ XU, const T *__restrict__ XM,
@@ -217,8 +220,9 @@ __global__ __launch_bounds__(64) void coeff_chunks_kernel(
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
     double *__restrict__ part, const double *__restrict__ pred) {
     typedef typename Vec<T, VEC>::type V;
-    const int64_t q = blockIdx.x;
-    if (q >= n_chunks || (pred && *pred == 0.0)) return;
+    if (pred && *pred == 0.0) return;
+    const int64_t stride = PERSIST ? (int64_t)gridDim.x : n_chunks;
+    for (int64_t q = blockIdx.x; q < n_chunks; q += stride) {
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     const int64_t row = chunk_row[q], b = chunk_begin[q], e = b + chunk_len[q];
     V xu[NV], pu[NV];
@@ -304,6 +308,7 @@ __global__ __launch_bounds__(64) void coeff_chunks_kernel(
         o[3] = c3;
         o[4] = c4;
     }
+    }
 }
 
 // Item regulariser lambda n_j ||xm_j + alpha pm_j||^2, n_j from the CSR of
@@ -372,6 +377,11 @@ __global__ __launch_bounds__(256) void coeff_itemreg_kernel(const int64_t *__res
 
 constexpr int kItemBlocks = 512;
 
+// Grid of a chunk kernel: one workgroup per chunk, or the plan's persistent grid.
+static unsigned chunk_grid(const Plan *p) {
+    return (unsigned)(p->grid > 0 ? std::min<int64_t>(p->grid, p->n_chunks) : p->n_chunks);
+}
+
 template <typename T, int VEC, int NV>
 int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
                  const T *U, const T *M, int n_f, int ld, double lambda, T *gU, T *gM,
@@ -392,11 +402,18 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
     T *partR = (T *)(ws + scal_bytes);
     T *partRt = (T *)(ws + scal_bytes + pR_bytes);
     if (doR) {
-        if (pR->n_chunks)
-            hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV>), dim3((unsigned)pR->n_chunks),
-                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, U, M, n_f, ld,
-                               lambda, pR->n_chunks, pR->chunk_row, pR->chunk_begin, pR->chunk_len,
-                               pR->chunk_slot, gU, partR, scal, 1, gU != nullptr ? 1 : 0);
+        if (pR->n_chunks) {
+#define ALS_GRAD_R(P)                                                                               \
+    hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV, P>), dim3(chunk_grid(pR)), dim3(kWave), 0, s, \
+                       R->indptr, R->indices, R->values, U, M, n_f, ld, lambda, pR->n_chunks,       \
+                       pR->chunk_row, pR->chunk_begin, pR->chunk_len, pR->chunk_slot, gU, partR,    \
+                       scal, 1, gU != nullptr ? 1 : 0)
+            if (pR->grid > 0)
+                ALS_GRAD_R(true);
+            else
+                ALS_GRAD_R(false);
+#undef ALS_GRAD_R
+        }
         if (pR->n_split_rows)
             hipLaunchKernelGGL((grad_split_kernel<T, NP>), dim3((unsigned)pR->n_split_rows),
                                dim3(kWave), 0, s, R->indptr, U, n_f, ld, lambda, pR->n_split_rows,
@@ -405,12 +422,18 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
     }
     if (doRt) {
         double *sc = scal + 2 * rowsR;
-        if (pRt->n_chunks)
-            hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV>), dim3((unsigned)pRt->n_chunks),
-                               dim3(kWave), 0, s, Rt->indptr, Rt->indices, Rt->values, M, U, n_f,
-                               ld, lambda, pRt->n_chunks, pRt->chunk_row, pRt->chunk_begin,
-                               pRt->chunk_len, pRt->chunk_slot, gM, partRt, sc, 0,
-                               gM != nullptr ? 1 : 0);
+        if (pRt->n_chunks) {
+#define ALS_GRAD_RT(P)                                                                               \
+    hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV, P>), dim3(chunk_grid(pRt)), dim3(kWave), 0, s, \
+                       Rt->indptr, Rt->indices, Rt->values, M, U, n_f, ld, lambda, pRt->n_chunks,    \
+                       pRt->chunk_row, pRt->chunk_begin, pRt->chunk_len, pRt->chunk_slot, gM,        \
+                       partRt, sc, 0, gM != nullptr ? 1 : 0)
+            if (pRt->grid > 0)
+                ALS_GRAD_RT(true);
+            else
+                ALS_GRAD_RT(false);
+#undef ALS_GRAD_RT
+        }
         if (pRt->n_split_rows)
             hipLaunchKernelGGL((grad_split_kernel<T, NP>), dim3((unsigned)pRt->n_split_rows),
                                dim3(kWave), 0, s, Rt->indptr, M, n_f, ld, lambda,
@@ -432,11 +455,17 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
     double *part =
         (double *)ctx->workspace((size_t)(rows * 5 + kSumStageDoubles) * sizeof(double), s, &err);
     if (!part) return err;
-    if (pR->n_chunks)
-        hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV>), dim3((unsigned)pR->n_chunks),
-                           dim3(kWave), 0, s, R->indptr, R->indices, R->values, U, M, PU, PM, n_f,
-                           ld, lambda, pR->n_chunks, pR->chunk_row, pR->chunk_begin,
-                           pR->chunk_len, part, pred);
+    if (pR->n_chunks) {
+#define ALS_COEF(P)                                                                                  \
+    hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV, P>), dim3(chunk_grid(pR)), dim3(kWave), 0, s, \
+                       R->indptr, R->indices, R->values, U, M, PU, PM, n_f, ld, lambda, pR->n_chunks, \
+                       pR->chunk_row, pR->chunk_begin, pR->chunk_len, part, pred)
+        if (pR->grid > 0)
+            ALS_COEF(true);
+        else
+            ALS_COEF(false);
+#undef ALS_COEF
+    }
     hipLaunchKernelGGL((coeff_itemreg_kernel<T, NV * VEC>), dim3(kItemBlocks), dim3(256), 0, s,
                        Rt->indptr, Rt->n_rows, M, PM, n_f, ld, lambda, part + 5 * pR->n_chunks,
                        pred);

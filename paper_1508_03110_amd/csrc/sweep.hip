@@ -24,6 +24,7 @@
 // so results do not depend on scheduling) before the solve.
 #include <math.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "internal.h"
@@ -284,20 +285,19 @@ template <typename T, int NB> struct Occ {
     static constexpr int waves = (sizeof(T) == 4 ? NB <= 7 : NB <= 4) ? 2 : 1;
 };
 
+// One chunk: Gram of its ratings, then either the partial tiles (split row)
+// or the row solve.
 template <typename T, int NB>
-__global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
-    const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
+__device__ __forceinline__ void sweep_chunk(
+    int64_t q, const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
-    T lambda, int64_t n_chunks, const int32_t *__restrict__ chunk_row,
-    const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
-    const int32_t *__restrict__ chunk_slot, typename Mfma<T>::acc4 *__restrict__ partial,
-    const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row,
-    int32_t *__restrict__ status, int empty_status, int vec) {
+    T lambda, const int32_t *__restrict__ chunk_row, const int64_t *__restrict__ chunk_begin,
+    const int32_t *__restrict__ chunk_len, const int32_t *__restrict__ chunk_slot,
+    typename Mfma<T>::acc4 *__restrict__ partial, const T *__restrict__ X_at,
+    T *__restrict__ grad_out, int64_t *__restrict__ bad_row, int32_t *__restrict__ status,
+    int empty_status, int vec, T *sm) {
     typedef typename Mfma<T>::acc4 acc4;
     typedef Tri<NB> TR;
-    __shared__ T sm[Shared<T, NB>::size];
-    const int64_t q = blockIdx.x;
-    if (q >= n_chunks) return;
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     int64_t row, b, len;
     int slot;
@@ -325,6 +325,34 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     const int64_t n_i = indptr[row + 1] - indptr[row];
     finish_row<T, NB>(A, row, n_i, X, n_f, ld, lambda, X_at, grad_out, bad_row, status,
                       empty_status, sm);
+}
+
+// One chunk per 64-lane workgroup (PERSIST = false), or a persistent grid
+// striding over the chunks (PERSIST = true; chunks are ordered longest
+// first, so the stride deals them out like a greedy schedule).
+// chunk_row == nullptr: chunk q is row q in full (fold-in and unplanned use).
+template <typename T, int NB, bool PERSIST>
+__global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
+    const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
+    const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
+    T lambda, int64_t n_chunks, const int32_t *__restrict__ chunk_row,
+    const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
+    const int32_t *__restrict__ chunk_slot, typename Mfma<T>::acc4 *__restrict__ partial,
+    const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row,
+    int32_t *__restrict__ status, int empty_status, int vec) {
+    __shared__ T sm[Shared<T, NB>::size];
+    if constexpr (PERSIST) {
+        for (int64_t q = blockIdx.x; q < n_chunks; q += gridDim.x)
+            sweep_chunk<T, NB>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row, chunk_begin,
+                               chunk_len, chunk_slot, partial, X_at, grad_out, bad_row, status,
+                               empty_status, vec, sm);
+    } else {
+        const int64_t q = blockIdx.x;
+        if (q >= n_chunks) return;
+        sweep_chunk<T, NB>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row, chunk_begin,
+                           chunk_len, chunk_slot, partial, X_at, grad_out, bad_row, status,
+                           empty_status, vec, sm);
+    }
 }
 
 // Second stage for rows split over several chunks: fixed-order sum of the
@@ -369,7 +397,7 @@ int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, in
     if (bad_row) hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, bad_row, (int64_t)LLONG_MAX);
     if (!plan) {
         if (n_rows_unplanned > 0)
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB>), dim3((unsigned)n_rows_unplanned),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false>), dim3((unsigned)n_rows_unplanned),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
                                lambda, n_rows_unplanned, nullptr, nullptr, nullptr, nullptr,
                                (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status, vec);
@@ -381,12 +409,21 @@ int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, in
         partial = (acc4 *)ctx->workspace((size_t)plan->n_slots * TR::NT * kWave * sizeof(acc4), s, &err);
         if (!partial) return err;
     }
-    if (plan->n_chunks > 0)
-        hipLaunchKernelGGL((sweep_chunks_kernel<T, NB>), dim3((unsigned)plan->n_chunks), dim3(kWave),
-                           0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld, lambda,
-                           plan->n_chunks, plan->chunk_row, plan->chunk_begin, plan->chunk_len,
-                           plan->chunk_slot, partial, X_at, grad_out, bad_row, status,
-                           empty_status, vec);
+    if (plan->n_chunks > 0) {
+        if (plan->grid > 0)
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true>),
+                               dim3((unsigned)std::min<int64_t>(plan->grid, plan->n_chunks)),
+                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
+                               lambda, plan->n_chunks, plan->chunk_row, plan->chunk_begin,
+                               plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
+                               status, empty_status, vec);
+        else
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false>), dim3((unsigned)plan->n_chunks),
+                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
+                               lambda, plan->n_chunks, plan->chunk_row, plan->chunk_begin,
+                               plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
+                               status, empty_status, vec);
+    }
     if (plan->n_split_rows > 0)
         hipLaunchKernelGGL((sweep_split_kernel<T, NB>), dim3((unsigned)plan->n_split_rows),
                            dim3(kWave), 0, s, R->indptr, X, n_f, ld, lambda, plan->n_split_rows,

@@ -54,9 +54,15 @@ class DeviceCsr:
 
     def __init__(self, ctx: Context, indptr, indices, values, n_cols: int, chunk: int = 0):
         dev = ctx.torch_device
-        self.indptr = torch.as_tensor(np.ascontiguousarray(indptr, dtype=np.int64)).to(dev)
-        self.indices = torch.as_tensor(np.ascontiguousarray(indices, dtype=np.int32)).to(dev)
-        self.values = torch.as_tensor(np.ascontiguousarray(values, dtype=np.float32)).to(dev)
+
+        def put(a, npt, tt):
+            if isinstance(a, torch.Tensor):  # already on the device: no host round trip
+                return a.to(device=dev, dtype=tt).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=npt)).to(dev)
+
+        self.indptr = put(indptr, np.int64, torch.int64)
+        self.indices = put(indices, np.int32, torch.int32)
+        self.values = put(values, np.float32, torch.float32)
         self.n_rows = int(self.indptr.numel() - 1)
         self.n_cols = int(n_cols)
         self.nnz = int(self.indices.numel())
@@ -72,7 +78,21 @@ class DeviceCsr:
         return cls(ctx, A.indptr, A.indices, A.values, A.n_cols, chunk)
 
     def info(self) -> dict:
-        return L.als_plan_info(self.plan)
+        d = L.als_plan_info(self.plan)
+        d["grid"] = getattr(self, "grid", 0)
+        return d
+
+    def replan(self, chunk: int = 0, grid: int = 0):
+        """Rebuild the row plan with another chunk size and set its launch grid."""
+        if self.plan:
+            L.als_plan_destroy(self.plan)
+            self.plan = None
+        self.plan = L.als_plan_create(self.ctx.handle, self.csr, int(chunk))
+        self.set_grid(grid)
+
+    def set_grid(self, grid: int):
+        L.als_plan_set_grid(self.plan, int(grid))
+        self.grid = int(grid)
 
     def close(self):
         if getattr(self, "plan", None):
@@ -116,8 +136,9 @@ class DeviceProblem:
 
     def pack(self, U, M):
         x = self.zeros()
-        self.U(x)[:, : self.n_f] = torch.as_tensor(np.asarray(U), dtype=self.dtype).to(x.device)
-        self.M(x)[:, : self.n_f] = torch.as_tensor(np.asarray(M), dtype=self.dtype).to(x.device)
+        for dst, a in ((self.U(x), U), (self.M(x), M)):
+            t = a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a))
+            dst[:, : self.n_f] = t.to(device=x.device, dtype=self.dtype)
         return x
 
     # -- single ABI calls

@@ -1,0 +1,123 @@
+"""Launch shapes and the billion-rating configuration.
+
+* A persistent grid (workgroups striding over the chunks) must give results
+  bit-identical to one workgroup per chunk: every chunk reduces into its own
+  slot in a fixed order.
+* At the full 10M x 1M, 1e9-rating shape (n_f = 50) both half-sweeps run in
+  the launch configuration the benchmark uses; sampled rows (random users,
+  the longest user, random items and the most-rated item, which is split
+  over many chunks) are recomputed one by one by the FP64 oracle from the
+  same FP32 inputs.  FP32 tolerance: 1e-4 relative per row.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1508_03110_amd.solver import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def n_cu():
+    return torch.cuda.get_device_properties(0).multi_processor_count
+
+
+def test_persistent_grid_is_bit_identical(ctx):
+    from paper_1508_03110_amd.solver import AlsNcg, DeviceProblem
+    P = synth.random_problem(300, 200, n_f=20, lam=0.05, seed=41, density=0.05, long_rows=4,
+                             long_len=190, empty_rows=5, x0_sigma=0.5)
+    U0, M0 = P.U0.astype(np.float32), P.M0.astype(np.float32)
+    runs = []
+    for grid in (0, 7, 64):
+        DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32, chunk=32)
+        DP.R.set_grid(grid)
+        DP.Rt.set_grid(grid)
+        s = AlsNcg(DP).init(U0, M0)
+        for _ in range(5):
+            s.step()
+        runs.append((s.x.clone(), s.pdir.clone(), s.f))
+    for x, p, f in runs[1:]:
+        assert torch.equal(x, runs[0][0]) and torch.equal(p, runs[0][1]) and f == runs[0][2]
+
+
+@pytest.mark.timeout(600)
+def test_billion_rating_half_sweeps_sampled(ctx):
+    from paper_1508_03110_amd.solver import DeviceCsr, DeviceProblem
+    from synth import scale
+    print("generating 1e9 ratings", flush=True)
+    R, U0, M0 = scale.generate(device=ctx.torch_device, log=lambda m: print(m, flush=True))
+    Rd = DeviceCsr(ctx, R.indptr, R.indices, R.values, R.n_m)
+    Rtd = DeviceCsr(ctx, R.indptr_t, R.indices_t, R.values_t, R.n_u)
+    DP = DeviceProblem(ctx, Rd, Rtd, 50, 0.05, torch.float32)
+    DP.R.set_grid(8 * n_cu())
+    DP.Rt.set_grid(8 * n_cu())
+    assert DP.R.nnz == 1_000_000_000 and DP.n_u == 10_000_000 and DP.n_m == 1_000_000
+    U = torch.empty((DP.n_u, 50), dtype=torch.float32, device=ctx.torch_device)
+    M = torch.empty((DP.n_m, 50), dtype=torch.float32, device=ctx.torch_device)
+    bad = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    DP.sweep("U", M0, U, bad_row=bad)
+    DP.sweep("M", U, M, bad_row=bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == (1 << 63) - 1
+    check_sampled(ctx, R.indptr, R.indices, R.values, R.indptr_t, R.indices_t, R.values_t,
+                  M0, U, M, DP.n_u, DP.n_m, 50, 0.05, seed=9, n_users=24, n_items=12)
+
+
+def check_sampled(ctx, ip_u, ix_u, va_u, ip_m, ix_m, va_m, M0, U, M, n_u, n_m, n_f, lam, seed,
+                  n_users, n_items, tol=1e-4):
+    """Sampled rows of both half-sweeps (random rows plus the longest row of
+    each orientation) recomputed by the FP64 oracle from the same FP32 inputs."""
+    dev = ctx.torch_device
+    rng = np.random.default_rng(seed)
+    lens_u = ip_u[1:] - ip_u[:-1]
+    lens_m = ip_m[1:] - ip_m[:-1]
+    users = sorted(set(rng.integers(0, n_u, n_users).tolist()) | {int(torch.argmax(lens_u))})
+    items = sorted(set(rng.integers(0, n_m, n_items).tolist()) | {int(torch.argmax(lens_m))})
+    for side, rows, ip, ix, va, Y, X in (("U", users, ip_u, ix_u, va_u, M0, U),
+                                         ("M", items, ip_m, ix_m, va_m, U, M)):
+        ipr = ip.cpu().numpy()
+        sel = np.concatenate([np.arange(ipr[r], ipr[r + 1]) for r in rows])
+        sel_t = torch.as_tensor(sel, device=dev)
+        ids = ix[sel_t].cpu().numpy()
+        vals = va[sel_t].cpu().numpy()
+        ptr = np.zeros(len(rows) + 1, dtype=np.int64)
+        ptr[1:] = np.cumsum([ipr[r + 1] - ipr[r] for r in rows])
+        cols, inv = np.unique(ids, return_inverse=True)
+        A = synth.Csr(len(rows), len(cols), ptr, inv.astype(np.int32), vals.astype(np.float32))
+        Ysub = Y[torch.as_tensor(cols, device=dev)][:, :n_f].cpu().numpy().astype(np.float64)
+        ref = oracle.half_sweep(A, Ysub, lam)
+        got = X[torch.as_tensor(rows, device=dev)][:, :n_f].cpu().numpy().astype(np.float64)
+        rel = np.linalg.norm(got - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
+        for k, r in enumerate(rows):
+            print(side, r, "len", ptr[k + 1] - ptr[k], "rel %.3e" % rel[k], flush=True)
+        assert rel.max() <= tol, side
+
+
+@pytest.mark.timeout(300)
+def test_ml20m_shape_half_sweeps_sampled(ctx):
+    """The 20M-rating shape in the benchmark's launch configuration (default
+    plans), including the most-rated item (137,241 ratings, split)."""
+    from paper_1508_03110_amd.solver import DeviceProblem
+    P = synth.c1_ml20m()
+    DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32)
+    dev = ctx.torch_device
+    M0 = torch.as_tensor(P.M0.astype(np.float32)).to(dev)
+    U = torch.empty((P.n_u, P.n_f), dtype=torch.float32, device=dev)
+    M = torch.empty((P.n_m, P.n_f), dtype=torch.float32, device=dev)
+    DP.sweep("U", M0, U)
+    DP.sweep("M", U, M)
+    torch.cuda.synchronize()
+    check_sampled(ctx, DP.R.indptr, DP.R.indices, DP.R.values, DP.Rt.indptr, DP.Rt.indices,
+                  DP.Rt.values, M0, U, M, P.n_u, P.n_m, P.n_f, P.lam, seed=8, n_users=24,
+                  n_items=12)
