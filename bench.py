@@ -44,7 +44,7 @@ def sweep_flops(nnz, n_rows, n_f):
 def kernel_source_hash():
     import hashlib
     m = hashlib.sha256()
-    for f in ("sweep.hip", "internal.h"):
+    for f in ("sweep.hip", "internal.h", "rowsolve.h"):
         with open(os.path.join(ROOT, "paper_1508_03110_amd", "csrc", f), "rb") as fh:
             m.update(fh.read())
     return m.hexdigest()[:16]

@@ -108,12 +108,13 @@ ALS_API size_t als_ctx_workspace_bytes(const als_ctx *ctx);
  */
 ALS_API int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **out);
 ALS_API void als_plan_destroy(als_plan *plan);
-/* Launch shape of the chunk kernels that use this plan (half-sweep,
- * gradient and coefficient passes): grid = 0 (default) launches one 64-lane
- * workgroup per chunk; grid > 0 launches min(grid, chunks) persistent
- * workgroups that stride over the chunks (longest first).  Results do not
- * depend on it (every chunk writes its own partials).  Used by the tuner. */
-ALS_API int als_plan_set_grid(als_plan *plan, int64_t grid);
+/* Launch shape of the chunk kernels that use this plan, for the half-sweep
+ * (sweep_grid) and for the gradient and coefficient passes (pass_grid):
+ * 0 (default) launches one 64-lane workgroup per chunk; > 0 launches
+ * min(grid, chunks) persistent workgroups that stride over the chunks
+ * (longest first).  Results do not depend on it (every chunk writes its own
+ * partials).  Used by the tuner. */
+ALS_API int als_plan_set_grid(als_plan *plan, int64_t sweep_grid, int64_t pass_grid);
 /* Plan statistics: out[0]=n_rows, [1]=nnz, [2]=n_chunks, [3]=split rows,
  * [4]=split chunks, [5]=chunk size, [6]=longest row. */
 ALS_API int als_plan_info(const als_plan *plan, int64_t out[7]);

@@ -50,7 +50,7 @@ _SIGS = {
     "als_ctx_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "als_plan_create": (_i, [_vp, _csrp, _i64, ctypes.POINTER(_vp)]),
     "als_plan_destroy": (None, [_vp]),
-    "als_plan_set_grid": (_i, [_vp, _i64]),
+    "als_plan_set_grid": (_i, [_vp, _i64, _i64]),
     "als_plan_info": (_i, [_vp, ctypes.POINTER(_i64)]),
     "als_sweep": (_i, [_vp, _vp, _csrp, _vp, _vp, _i, _i, _d, _i, _vp, _vp, _vp, _vp]),
     "als_sweep_mixed": (_i, [_vp, _vp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _vp, _vp]),
@@ -158,8 +158,8 @@ def als_plan_destroy(plan):
     load().als_plan_destroy(plan)
 
 
-def als_plan_set_grid(plan, grid):
-    return _check("als_plan_set_grid", load().als_plan_set_grid(plan, int(grid)))
+def als_plan_set_grid(plan, sweep_grid, pass_grid=0):
+    return _check("als_plan_set_grid", load().als_plan_set_grid(plan, int(sweep_grid), int(pass_grid)))
 
 
 def als_plan_info(plan) -> dict:

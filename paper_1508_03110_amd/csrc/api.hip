@@ -125,9 +125,11 @@ void als_plan_destroy(als_plan *p) {
     delete p;
 }
 
-int als_plan_set_grid(als_plan *p, int64_t grid) {
-    if (!p || grid < 0 || grid > INT32_MAX) return ALS_E_INVAL;
-    p->grid = grid;
+int als_plan_set_grid(als_plan *p, int64_t sweep_grid, int64_t pass_grid) {
+    if (!p || sweep_grid < 0 || sweep_grid > INT32_MAX || pass_grid < 0 || pass_grid > INT32_MAX)
+        return ALS_E_INVAL;
+    p->grid = sweep_grid;
+    p->grid_pass = pass_grid;
     return ALS_OK;
 }
 

@@ -91,9 +91,9 @@ template <typename T> __device__ inline T sum64(T v) { return sum4g(sum16(v)); }
 struct Plan {
     int64_t n_rows = 0, nnz = 0, n_chunks = 0, n_split_rows = 0, n_slots = 0, chunk = 0,
             max_row = 0;
-    // persistent grid of the chunk kernels (workgroups striding over the
-    // chunks); 0: one workgroup per chunk
-    int64_t grid = 0;
+    // persistent grids (workgroups striding over the chunks) of the
+    // half-sweep and of the streaming passes; 0: one workgroup per chunk
+    int64_t grid = 0, grid_pass = 0;
     // device arrays, chunk order = longest first
     int32_t *chunk_row = nullptr;
     int64_t *chunk_begin = nullptr;

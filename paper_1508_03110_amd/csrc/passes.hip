@@ -377,9 +377,10 @@ __global__ __launch_bounds__(256) void coeff_itemreg_kernel(const int64_t *__res
 
 constexpr int kItemBlocks = 512;
 
-// Grid of a chunk kernel: one workgroup per chunk, or the plan's persistent grid.
+// Grid of a streaming-pass chunk kernel: one workgroup per chunk, or the
+// plan's persistent grid.
 static unsigned chunk_grid(const Plan *p) {
-    return (unsigned)(p->grid > 0 ? std::min<int64_t>(p->grid, p->n_chunks) : p->n_chunks);
+    return (unsigned)(p->grid_pass > 0 ? std::min<int64_t>(p->grid_pass, p->n_chunks) : p->n_chunks);
 }
 
 template <typename T, int VEC, int NV>
@@ -408,7 +409,7 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
                        R->indptr, R->indices, R->values, U, M, n_f, ld, lambda, pR->n_chunks,       \
                        pR->chunk_row, pR->chunk_begin, pR->chunk_len, pR->chunk_slot, gU, partR,    \
                        scal, 1, gU != nullptr ? 1 : 0)
-            if (pR->grid > 0)
+            if (pR->grid_pass > 0)
                 ALS_GRAD_R(true);
             else
                 ALS_GRAD_R(false);
@@ -428,7 +429,7 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
                        Rt->indptr, Rt->indices, Rt->values, M, U, n_f, ld, lambda, pRt->n_chunks,    \
                        pRt->chunk_row, pRt->chunk_begin, pRt->chunk_len, pRt->chunk_slot, gM,        \
                        partRt, sc, 0, gM != nullptr ? 1 : 0)
-            if (pRt->grid > 0)
+            if (pRt->grid_pass > 0)
                 ALS_GRAD_RT(true);
             else
                 ALS_GRAD_RT(false);
@@ -456,11 +457,18 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
         (double *)ctx->workspace((size_t)(rows * 5 + kSumStageDoubles) * sizeof(double), s, &err);
     if (!part) return err;
     if (pR->n_chunks) {
-#define ALS_COEF(P)                                                                                  \
-    hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV, P>), dim3(chunk_grid(pR)), dim3(kWave), 0, s, \
-                       R->indptr, R->indices, R->values, U, M, PU, PM, n_f, ld, lambda, pR->n_chunks, \
-                       pR->chunk_row, pR->chunk_begin, pR->chunk_len, part, pred)
-        if (pR->grid > 0)
+        // a predicated pass (launched in every iteration, needed only after a
+        // restart) always takes a persistent grid, so that when it is off it
+        // costs a few thousand empty workgroups instead of one per chunk
+        unsigned grid = chunk_grid(pR);
+        const bool persist = pR->grid_pass > 0 || pred != nullptr;
+        if (pred && pR->grid_pass <= 0)
+            grid = (unsigned)std::min<int64_t>(pR->n_chunks, (int64_t)ctx->num_cu * 16);
+#define ALS_COEF(P)                                                                             \
+    hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV, P>), dim3(grid), dim3(kWave), 0, s,       \
+                       R->indptr, R->indices, R->values, U, M, PU, PM, n_f, ld, lambda,         \
+                       pR->n_chunks, pR->chunk_row, pR->chunk_begin, pR->chunk_len, part, pred)
+        if (persist)
             ALS_COEF(true);
         else
             ALS_COEF(false);

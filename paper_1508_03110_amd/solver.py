@@ -80,19 +80,22 @@ class DeviceCsr:
     def info(self) -> dict:
         d = L.als_plan_info(self.plan)
         d["grid"] = getattr(self, "grid", 0)
+        d["grid_pass"] = getattr(self, "grid_pass", 0)
         return d
 
-    def replan(self, chunk: int = 0, grid: int = 0):
-        """Rebuild the row plan with another chunk size and set its launch grid."""
+    def replan(self, chunk: int = 0, grid: int = 0, grid_pass: int = 0):
+        """Rebuild the row plan with another chunk size and set its launch grids."""
         if self.plan:
             L.als_plan_destroy(self.plan)
             self.plan = None
         self.plan = L.als_plan_create(self.ctx.handle, self.csr, int(chunk))
-        self.set_grid(grid)
+        self.set_grid(grid, grid_pass)
 
-    def set_grid(self, grid: int):
-        L.als_plan_set_grid(self.plan, int(grid))
-        self.grid = int(grid)
+    def set_grid(self, grid: int, grid_pass: int = 0):
+        """Persistent grids of the half-sweep and of the streaming passes (0: one
+        workgroup per chunk)."""
+        L.als_plan_set_grid(self.plan, int(grid), int(grid_pass))
+        self.grid, self.grid_pass = int(grid), int(grid_pass)
 
     def close(self):
         if getattr(self, "plan", None):

@@ -1,15 +1,17 @@
-"""Work-decomposition tuner for the half-sweep.
+"""Work-decomposition tuner for the half-sweep and the streaming passes.
 
 For each orientation of R it times the half-sweep (the dominant launch of
 both algorithms) over a small grid of launch shapes and keeps the fastest:
   * chunk: the most ratings one wavefront takes from a row (longer rows are
-    split with a fixed-order second stage); candidates around the plan's
-    default of nnz / (8 x compute units);
-  * grid: one workgroup per chunk, or a persistent grid of k workgroups per
-    compute unit striding over the chunks (longest first).
-Results do not depend on the choice (every chunk reduces into its own slot
-in a fixed order); only time does.  The choice is returned as a dict and
-applied to the problem's plans.
+    split with a fixed-order second stage); candidates at and below the
+    plan's default (nnz / (8 x compute units), at most 8192);
+  * sweep grid: one workgroup per chunk, or a persistent grid of k
+    workgroups per compute unit striding over the chunks (longest first).
+With that plan it then picks the persistent grid of the orientation's
+streaming pass (coefficients for R, gradient for R^T), whose per-chunk work
+is small enough for workgroup dispatch to matter.
+Results do not depend on any of these choices (every chunk reduces into its
+own slot in a fixed order); only time does.
 """
 from __future__ import annotations
 
@@ -18,44 +20,65 @@ import time
 import torch
 
 
-def _time_sweep(DP, side, Y, X, reps):
-    DP.sweep(side, Y, X)  # warm (also sizes the workspace)
+def _best_ms(fn, reps):
+    fn()  # warm (also sizes the workspace)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     best = float("inf")
     for _ in range(reps):
         a.record()
-        DP.sweep(side, Y, X)
+        fn()
         b.record()
         torch.cuda.synchronize()
         best = min(best, a.elapsed_time(b))
     return best
 
 
-def tune(DP, x, reps: int = 2, chunk_factors=(1.0, 0.25, 0.0625), grids_per_cu=(0, 4, 8, 16),
-         log=None) -> dict:
-    """Tune both plans of DeviceProblem DP on the iterate x ([U; M], its
-    current values are used as the fixed side; X outputs go to scratch)."""
+def tune(DP, x, reps: int = 2, chunk_factors=(1.0, 0.25), grids_per_cu=(0, 4, 8, 16),
+         pass_grids_per_cu=(0, 4, 8, 16, 32), log=None) -> dict:
+    """Tune both plans of DeviceProblem DP around the iterate x ([U; M]; its
+    values are the inputs, outputs go to scratch buffers)."""
     say = log or (lambda *a: None)
     n_cu = torch.cuda.get_device_properties(DP.ctx.torch_device).multi_processor_count
+    dev = DP.ctx.torch_device
     out = {}
-    for side, A, Y, nrows in (("U", DP.R, DP.M(x), DP.n_u), ("M", DP.Rt, DP.U(x), DP.n_m)):
-        X = torch.empty((nrows, DP.ld), dtype=DP.dtype, device=DP.ctx.torch_device)
+    U, M = DP.U(x), DP.M(x)
+    # a direction distinct from x: the coefficient pass gathers both, and
+    # p = x would let the second gather hit the first one's cache lines
+    pdir = torch.empty_like(x).normal_(0.0, 0.01)
+    pU, pM = DP.U(pdir), DP.M(pdir)
+    coef = torch.zeros(8, dtype=torch.float64, device=dev)
+    for side, A, Y, nrows in (("U", DP.R, M, DP.n_u), ("M", DP.Rt, U, DP.n_m)):
+        X = torch.empty((nrows, DP.ld), dtype=DP.dtype, device=dev)
         base = A.info()["chunk"]
         trials = []
         t0 = time.perf_counter()
         for f in chunk_factors:
             chunk = max(256, int(base * f) // 4 * 4)
-            A.replan(chunk, 0)
+            A.replan(chunk, 0, 0)
             for gpc in grids_per_cu:
-                A.set_grid(gpc * n_cu)
-                ms = _time_sweep(DP, side, Y, X, reps)
+                A.set_grid(gpc * n_cu, 0)
+                ms = _best_ms(lambda: DP.sweep(side, Y, X), reps)
                 trials.append({"chunk": chunk, "grid": gpc * n_cu, "ms": round(ms, 4)})
         best = min(trials, key=lambda t: t["ms"])
-        A.replan(best["chunk"], best["grid"])
-        out[side] = {"best": best, "default_ms": trials[0]["ms"], "trials": trials,
+        A.replan(best["chunk"], best["grid"], 0)
+        if side == "U":  # the coefficient pass runs over R
+            run = lambda: DP.coeffs(U, M, pU, pM, coef)  # noqa: E731
+        else:            # the M-block gradient pass runs over R^T
+            run = lambda: DP.gradient(U, M, None, X, None)  # noqa: E731
+        ptrials = []
+        for gpc in pass_grids_per_cu:
+            A.set_grid(best["grid"], gpc * n_cu)
+            ptrials.append({"grid_pass": gpc * n_cu, "ms": round(_best_ms(run, reps), 4)})
+        pbest = min(ptrials, key=lambda t: t["ms"])
+        A.set_grid(best["grid"], pbest["grid_pass"])
+        out[side] = {"best": dict(best, grid_pass=pbest["grid_pass"], pass_ms=pbest["ms"]),
+                     "default_ms": trials[0]["ms"], "default_pass_ms": ptrials[0]["ms"],
+                     "trials": trials, "pass_trials": ptrials,
                      "seconds": round(time.perf_counter() - t0, 2)}
-        say("tuned %s half-sweep: %s (default %.3f ms)" % (side, best, trials[0]["ms"]))
+        say("tuned %s: %s (default sweep %.3f ms, pass %.3f ms)"
+            % (side, out[side]["best"], trials[0]["ms"], ptrials[0]["ms"]))
         del X
+    del pdir
     return out

@@ -41,8 +41,8 @@ def test_persistent_grid_is_bit_identical(ctx):
     runs = []
     for grid in (0, 7, 64):
         DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32, chunk=32)
-        DP.R.set_grid(grid)
-        DP.Rt.set_grid(grid)
+        DP.R.set_grid(grid, grid)
+        DP.Rt.set_grid(grid, grid)
         s = AlsNcg(DP).init(U0, M0)
         for _ in range(5):
             s.step()
