@@ -221,6 +221,12 @@ def c3_bench(ctx, steps=20, gtol=1e-6, max_iter=400):
             for _ in range(K):
                 s.step()
                 fk.append(DP.loss_and_gnorm(s.x)[0])
+            def rmse():
+                U = DP.U(s.x)[:, :n_f].cpu().numpy().astype(np.float64)
+                M = DP.M(s.x)[:, :n_f].cpu().numpy().astype(np.float64)
+                return float(np.sqrt(np.mean((np.einsum("ij,ij->i", U[hr], M[hc]) - hv64) ** 2)))
+
+            e["heldout_rmse_after_%d" % K] = rmse()
             if r:
                 e["rel_f_err_vs_fp64"] = [abs(a - b) / b for a, b in zip(fk, r["als_ncg_f"][1:])]
                 Us = DP.U(s.x)[torch.as_tensor(r["sample_users"], device=DP.ctx.torch_device), :n_f]
@@ -237,9 +243,7 @@ def c3_bench(ctx, steps=20, gtol=1e-6, max_iter=400):
             torch.cuda.synchronize()
             e["ms_per_iteration"] = (time.perf_counter() - t) / steps * 1e3
             e["phase_ms"] = {k: round(v, 4) for k, v in s.phase_ms().items()}
-            U = DP.U(s.x)[:, :n_f].cpu().numpy().astype(np.float64)
-            M = DP.M(s.x)[:, :n_f].cpu().numpy().astype(np.float64)
-            e["heldout_rmse"] = float(np.sqrt(np.mean((np.einsum("ij,ij->i", U[hr], M[hc]) - hv64) ** 2)))
+            e["heldout_rmse_after_%d" % (K + steps)] = rmse()
             e["f_after"] = {"iterations": K + steps, "f": DP.loss_and_gnorm(s.x)[0]}
             del s
             # time to (1/N)||g|| <= gtol from x0: traced run, then a timed run

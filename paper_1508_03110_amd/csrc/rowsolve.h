@@ -20,6 +20,22 @@
 
 namespace alsncg {
 
+// LDS ordering between the steps of a row solve.  WS = false: a workgroup
+// barrier (the solving wavefront is the whole workgroup).  WS = true: the
+// solving wavefront shares its workgroup with a wavefront doing other work,
+// so only the wavefront's own LDS accesses are ordered (a wavefront's LDS
+// instructions complete in order; the fences keep the compiler from moving
+// accesses across the step).
+template <bool WS> __device__ __forceinline__ void row_sync() {
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <int NB> struct Tri {
     static constexpr int NT = NB * (NB + 1) / 2;
     __host__ __device__ static constexpr int id(int a, int b) { return a * NB - a * (a - 1) / 2 + (b - a); }
@@ -37,7 +53,7 @@ template <typename T, int NB> struct Shared {
 template <typename T, int NB>
 __device__ __forceinline__ void regularize(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT], T reg,
                                            int n_f) {
-    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
@@ -55,19 +71,19 @@ __device__ __forceinline__ void regularize(typename Mfma<T>::acc4 (&A)[Tri<NB>::
 // A(a, b) -= R(kb, a)^T R(kb, b) 4 more (the contraction index of an MFMA
 // is a free label, so accumulator registers are fed back as operands).
 // Returns true when a pivot is not positive (the matrix is not SPD).
-template <typename T, int NB>
+template <typename T, int NB, bool WS = false>
 __device__ __forceinline__ bool cholesky_blocked(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
                                                  int n_f, T *Dt, T *Yinv) {
     typedef Tri<NB> TR;
     typedef Mfma<T> MF;
     constexpr int TS = Shared<T, NB>::TS;
-    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     bool bad = false;
 #pragma unroll
     for (int kb = 0; kb < NB; ++kb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) Dt[MF::row(g, r) * 17 + c] = A[TR::id(kb, kb)][r];
-        __syncthreads();
+        row_sync<WS>();
         T p[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i)
@@ -88,7 +104,7 @@ __device__ __forceinline__ bool cholesky_blocked(typename Mfma<T>::acc4 (&A)[Tri
                 for (int i = kk + 1; i < 16; ++i) p[i] -= rk[i] * p[kk];
             }
         }
-        __syncthreads();
+        row_sync<WS>();
         if (lane < 16) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) Dt[i * 17 + lane] = p[i];
@@ -96,7 +112,7 @@ __device__ __forceinline__ bool cholesky_blocked(typename Mfma<T>::acc4 (&A)[Tri
 #pragma unroll
             for (int i = 0; i < 16; ++i) Yinv[kb * TS + i * 17 + (lane - 16)] = p[i];
         }
-        __syncthreads();
+        row_sync<WS>();
 #pragma unroll
         for (int r = 0; r < 4; ++r) A[TR::id(kb, kb)][r] = Dt[MF::row(g, r) * 17 + c];
         if (kb + 1 < NB) {
@@ -119,7 +135,7 @@ __device__ __forceinline__ bool cholesky_blocked(typename Mfma<T>::acc4 (&A)[Tri
                 for (int s4 = 0; s4 < 4; ++s4)
                     A[TR::id(a, bb)] = Mfma<T>::mma(-A[TR::id(kb, a)][s4], A[TR::id(kb, bb)][s4],
                                                     A[TR::id(a, bb)]);
-        __syncthreads();
+        row_sync<WS>();
     }
     return bad;
 }
@@ -129,16 +145,16 @@ __device__ __forceinline__ bool cholesky_blocked(typename Mfma<T>::acc4 (&A)[Tri
 // x_kb = R_kk^{-1} z_kb = Y^T z_kb with the stored Y = R_kk^{-T}.
 // z, x: LDS vectors of NB*16 in slot order (x must not alias z); slots past
 // n_f of x come out zero.
-template <typename T, int NB>
+template <typename T, int NB, bool WS = false>
 __device__ __forceinline__ void back_solve(const typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
                                            int n_f, const T *z, T *x, const T *Yinv) {
     typedef Tri<NB> TR;
     typedef Mfma<T> MF;
     constexpr int NP = NB * 16;
     constexpr int TS = Shared<T, NB>::TS;
-    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     for (int k = lane; k < NP; k += kWave) x[k] = T(0);
-    __syncthreads();
+    row_sync<WS>();
 #pragma unroll
     for (int kb = NB - 1; kb >= 0; --kb) {
         if (16 * kb < n_f) {
@@ -158,7 +174,7 @@ __device__ __forceinline__ void back_solve(const typename Mfma<T>::acc4 (&A)[Tri
             }
             xp = sum4g(xp);
             if (g == 0 && 16 * kb + c < n_f) x[16 * kb + c] = xp;
-            __syncthreads();
+            row_sync<WS>();
         }
     }
 }
@@ -167,13 +183,13 @@ __device__ __forceinline__ void back_solve(const typename Mfma<T>::acc4 (&A)[Tri
 // for kb = 0, 1, ...: t = w_kb - sum_{a < kb} R(a, kb)^T z_a, z_kb = R_kk^{-T} t.
 // w, z: LDS vectors of NB*16 in slot order (z must not alias w); tmp: 16
 // elements of LDS scratch.  Slots past n_f of z come out zero.
-template <typename T, int NB>
+template <typename T, int NB, bool WS = false>
 __device__ __forceinline__ void forward_solve(const typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
                                               int n_f, const T *w, T *z, const T *Yinv, T *tmp) {
     typedef Tri<NB> TR;
     typedef Mfma<T> MF;
     constexpr int TS = Shared<T, NB>::TS;
-    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
 #pragma unroll
     for (int kb = 0; kb < NB; ++kb) {
         if (16 * kb < n_f) {
@@ -184,7 +200,7 @@ __device__ __forceinline__ void forward_solve(const typename Mfma<T>::acc4 (&A)[
                 for (int r = 0; r < 4; ++r) t += A[TR::id(a, kb)][r] * z[16 * a + MF::row(g, r)];
             t = sum4g(t);
             if (g == 0) tmp[c] = (16 * kb + c < n_f) ? w[16 * kb + c] - t : T(0);
-            __syncthreads();
+            row_sync<WS>();
             T zp = T(0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -193,12 +209,12 @@ __device__ __forceinline__ void forward_solve(const typename Mfma<T>::acc4 (&A)[
             }
             zp = sum4g(zp);
             if (g == 0) z[16 * kb + c] = (16 * kb + c < n_f) ? zp : T(0);
-            __syncthreads();
+            row_sync<WS>();
         } else if (g == 0) {
             z[16 * kb + c] = T(0);
         }
     }
-    __syncthreads();
+    row_sync<WS>();
 }
 
 }  // namespace alsncg

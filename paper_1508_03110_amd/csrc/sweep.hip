@@ -180,7 +180,7 @@ __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<
 
 // Regularise, optionally form the gradient 2 (A x_in - v), factorise, solve
 // and store one row.  `sm` is Shared<T, NB>::size elements of LDS.
-template <typename T, int NB>
+template <typename T, int NB, bool WS = false>
 __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT], int64_t row,
                                            int64_t n_i, T *__restrict__ X, int n_f, int ld,
                                            T lambda, const T *__restrict__ X_at,
@@ -190,7 +190,7 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
     typedef Tri<NB> TR;
     typedef Mfma<T> MF;
     constexpr int NP = NB * 16;
-    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     T *xs = sm;
     T *ys = sm + NP;
     T *w = sm + 2 * NP;  // v during the gradient (shares space with the factor scratch)
@@ -212,7 +212,7 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
         // y = A x_in (A symmetric, upper tiles only), then g = 2 (y - v).
         const T *xin = X_at ? X_at + row * (int64_t)ld : xrow;
         for (int k = lane; k < NP; k += kWave) xs[k] = (k < n_f) ? xin[Slots<NB>::col(k)] : T(0);
-        __syncthreads();
+        row_sync<WS>();
         // row-block a of A x: tiles (a, b >= a) times x_b, reduced over the 16
         // lanes of a quarter-wave as soon as the block row is done; the
         // transposed contributions of the upper tiles to block b collect in cacc
@@ -245,22 +245,22 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
 #pragma unroll
                 for (int r = 0; r < 4; ++r) w[16 * a + MF::row(g, r)] = A[TR::id(a, NB - 1)][r];
         }
-        __syncthreads();
+        row_sync<WS>();
         if (g == 0) {
 #pragma unroll
             for (int a = 0; a < NB; ++a) ys[16 * a + c] += cacc[a];
         }
-        __syncthreads();
+        row_sync<WS>();
         for (int k = lane; k < n_f; k += kWave)
             grad_out[row * (int64_t)ld + Slots<NB>::col(k)] = T(2) * (ys[k] - w[k]);
-        __syncthreads();
+        row_sync<WS>();
     }
 
     // ---- blocked Cholesky A = R^T R of the augmented matrix (pivots 0 .. n_f-1);
     // column n_f of the factor is then z with R^T z = v.
     T *Dt = sm + 2 * NP;
     T *Yinv = Dt + Shared<T, NB>::TS;
-    const bool bad = cholesky_blocked<T, NB>(A, n_f, Dt, Yinv);
+    const bool bad = cholesky_blocked<T, NB, WS>(A, n_f, Dt, Yinv);
 
     // ---- back substitution R x = z
     if (c == caug) {
@@ -269,7 +269,7 @@ __device__ __forceinline__ void finish_row(typename Mfma<T>::acc4 (&A)[Tri<NB>::
 #pragma unroll
             for (int r = 0; r < 4; ++r) ys[16 * a + MF::row(g, r)] = A[TR::id(a, NB - 1)][r];
     }
-    back_solve<T, NB>(A, n_f, ys, xs, Yinv);
+    back_solve<T, NB, WS>(A, n_f, ys, xs, Yinv);
     for (int k = lane; k < n_f; k += kWave) xrow[Slots<NB>::col(k)] = bad ? T(NAN) : xs[k];
     if (lane == 0) {
         if (bad && bad_row) atomicMin((unsigned long long *)bad_row, (unsigned long long)row);

@@ -527,7 +527,12 @@ __global__ __launch_bounds__(64, (OccMx<NB>::waves)) void sweep_mixed_split_kern
     }
 }
 
-// Split rows, stage 3: residual partial of one split chunk at x0.
+// Split rows, stage 3: residual partials at x0.  Each split chunk is cut
+// into kResPieces pieces of at most ceil(len / kResPieces) ratings, one
+// wavefront each (piece p of slot k writes rpart[k * kResPieces + p]), so the
+// longest chunk does not leave a latency-bound tail.
+constexpr int kResPieces = 8;
+
 template <int NB>
 __global__ __launch_bounds__(64) void mixed_residual_kernel(
     MixArgs a, int64_t n_slots, const int32_t *__restrict__ slot_chunk,
@@ -535,18 +540,22 @@ __global__ __launch_bounds__(64) void mixed_residual_kernel(
     const int32_t *__restrict__ chunk_len, float *__restrict__ rpart) {
     typedef SharedMx<NB> SM;
     __shared__ float xn[SM::NPV];
-    const int64_t k = blockIdx.x;
+    const int64_t w = blockIdx.x;
+    const int64_t k = w / kResPieces;
+    const int piece = (int)(w % kResPieces);
     if (k >= n_slots) return;
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
     const int32_t q = slot_chunk[k];
     const int64_t row = chunk_row[q];
-    const int64_t b = chunk_begin[q];
     const int64_t len = chunk_len[q];
+    const int64_t per = (len + kResPieces - 1) / kResPieces;
+    const int64_t b = chunk_begin[q] + min(len, piece * per);
+    const int64_t e = chunk_begin[q] + min(len, (piece + 1) * per);
     for (int i = lane; i < SM::NPV; i += kWave) xn[i] = i < a.n_f ? a.X32[row * (int64_t)a.ld + i] : 0.0f;
     __syncthreads();
     float res[SM::NV][4];
-    residual_stream<NB>(res, a.idx, a.val, b, b + len, a.Y32, a.ld, a.n_f, xn, g, c, a.vec32 != 0);
-    write_residual<NB>(res, rpart + k * (int64_t)SM::NPV, a.n_f);
+    residual_stream<NB>(res, a.idx, a.val, b, e, a.Y32, a.ld, a.n_f, xn, g, c, a.vec32 != 0);
+    write_residual<NB>(res, rpart + w * (int64_t)SM::NPV, a.n_f);
 }
 
 // Split rows, stage 4: fixed-order sum of the residual partials and the
@@ -580,7 +589,7 @@ __global__ __launch_bounds__(64, (OccMx<NB>::waves)) void mixed_correct_kernel(
         xs[k] = k < n_f ? a.X32[row * (int64_t)a.ld + Slots16<NB>::col(k)] : 0.0f;
     for (int i = lane; i < SM::NPV; i += kWave) {
         float acc = 0.0f;
-        for (int u = 0; u < ns; ++u) acc += rpart[(s0 + u) * (int64_t)SM::NPV + i];
+        for (int u = 0; u < ns * kResPieces; ++u) acc += rpart[(s0 * kResPieces + u) * (int64_t)SM::NPV + i];
         wn[i] = acc;
     }
     __syncthreads();
@@ -600,7 +609,7 @@ int run_mixed(Ctx *ctx, const Plan *plan, const als_csr *R, const MixArgs &a, hi
     if (plan->n_slots > 0) {
         const size_t p_bytes = align_up((size_t)plan->n_slots * TR::NT * kWave * sizeof(acc4), 256);
         const size_t f_bytes = a.refine ? align_up((size_t)plan->n_split_rows * FStore<NB>::floats * 4, 256) : 0;
-        const size_t r_bytes = a.refine ? (size_t)plan->n_slots * SharedMx<NB>::NPV * 4 : 0;
+        const size_t r_bytes = a.refine ? (size_t)plan->n_slots * kResPieces * SharedMx<NB>::NPV * 4 : 0;
         int err = ALS_OK;
         char *ws = (char *)ctx->workspace(p_bytes + f_bytes + r_bytes, s, &err);
         if (!ws) return err;
@@ -617,7 +626,7 @@ int run_mixed(Ctx *ctx, const Plan *plan, const als_csr *R, const MixArgs &a, hi
                            dim3(kWave), 0, s, a, plan->n_split_rows, plan->split_row,
                            plan->split_slot0, plan->split_nslot, (const acc4 *)partial, fstore);
         if (a.refine) {
-            hipLaunchKernelGGL((mixed_residual_kernel<NB>), dim3((unsigned)plan->n_slots), dim3(kWave),
+            hipLaunchKernelGGL((mixed_residual_kernel<NB>), dim3((unsigned)(plan->n_slots * kResPieces)), dim3(kWave),
                                0, s, a, plan->n_slots, plan->slot_chunk, plan->chunk_row,
                                plan->chunk_begin, plan->chunk_len, rpart);
             hipLaunchKernelGGL((mixed_correct_kernel<NB>), dim3((unsigned)plan->n_split_rows),
