@@ -411,8 +411,8 @@ def main():
                           "launches": 5}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design "
-              "is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (how the path would shard "
+              "is written up with the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

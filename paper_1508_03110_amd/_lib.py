@@ -81,11 +81,11 @@ _lib = None
 
 
 def load():
-    """Load libalsncg.so (built in-tree by __graft_entry__.build())."""
+    """Load libalsncg.so (built in-tree by paper_1508_03110_amd/build.py)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError("libalsncg.so is not built (%s): run __graft_entry__.build()" % LIB_PATH)
+            raise ImportError("libalsncg.so is not built (%s): run paper_1508_03110_amd/build.py" % LIB_PATH)
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(lib, name)
