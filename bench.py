@@ -130,16 +130,24 @@ def time_to_tol(DP, P, fstar, tol=1e-6, gtol=1e-6, max_als=2500, max_ncg=600):
         if kf is not None and kg is not None:
             break
     k_als = crossing(trace)
-    # ALS-NCG trace: f(x_k) = Q(alpha_k) and ||g_k|| come with every iteration
-    ncg = AlsNcg(DP).init(U0, M0)
-    trace_n = []
-    for k in range(1, max_ncg + 1):
-        ncg.step()
-        trace_n.append((k, ncg.f, ncg.gnorm()))
-        kf, kg = crossing(trace_n)
-        if kf is not None and kg is not None:
-            break
+    # ALS-NCG traces (backtracking of Algorithm 4, and the exact minimiser of
+    # the same quartic): f(x_k) = Q(alpha_k) and ||g_k|| come with every iteration
+    def ncg_trace(search):
+        ncg = AlsNcg(DP, search=search).init(U0, M0)
+        tr = []
+        for k in range(1, max_ncg + 1):
+            ncg.step()
+            f = ncg.f if ncg.f == ncg.f else DP.loss_and_gnorm(ncg.x)[0]  # NaN after an ALS point
+            tr.append((k, f, ncg.gnorm()))
+            kf, kg = crossing(tr)
+            if kf is not None and kg is not None:
+                break
+        return tr
+
+    trace_n = ncg_trace("backtracking")
     k_ncg = crossing(trace_n)
+    trace_e = ncg_trace("exact")
+    k_exact = crossing(trace_e)
 
     def timed(make, step, marks):
         marks = sorted({m for m in marks if m})
@@ -158,14 +166,18 @@ def time_to_tol(DP, P, fstar, tol=1e-6, gtol=1e-6, max_als=2500, max_ncg=600):
 
     ta = timed(lambda: Als(DP, DP.pack(U0, M0)), lambda s: s.sweep(), k_als)
     tn = timed(lambda: AlsNcg(DP).init(U0, M0), lambda s: s.step(), k_ncg)
-    for name, ks, ts, tr in (("als", k_als, ta, trace), ("als_ncg", k_ncg, tn, trace_n)):
+    te = timed(lambda: AlsNcg(DP, search="exact").init(U0, M0), lambda s: s.step(), k_exact)
+    for name, ks, ts, tr in (("als", k_als, ta, trace), ("als_ncg", k_ncg, tn, trace_n),
+                             ("als_ncg_exact_search", k_exact, te, trace_e)):
         out[name] = {"iterations_to_f_tol": ks[0], "seconds_to_f_tol": ts.get(ks[0]),
                      "iterations_to_g_tol": ks[1], "seconds_to_g_tol": ts.get(ks[1]),
                      "final_f": tr[-1][1], "final_gnorm_over_N": tr[-1][2] / N,
                      "traced_iterations": len(tr)}
     for crit in ("f_tol", "g_tol"):
         a, b = out["als"]["seconds_to_" + crit], out["als_ncg"]["seconds_to_" + crit]
+        e = out["als_ncg_exact_search"]["seconds_to_" + crit]
         out["speedup_" + crit] = (a / b) if (a and b) else None
+        out["speedup_exact_search_" + crit] = (a / e) if (a and e) else None
     return out
 
 

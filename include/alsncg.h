@@ -200,6 +200,18 @@ ALS_API int linesearch_coeffs(als_ctx *ctx, const als_plan *plan_R, const als_cs
                       int ld, double lambda, als_dtype dt, double *coeffs, void *stream);
 
 /*
+ * Exact line search on the same quartic (a stronger search than Algorithm 4,
+ * like the one the paper's serial runs use): alpha_out = the global minimiser
+ * over alpha > 0 of Q(alpha) = sum coeffs[n] alpha^n, from the real roots of
+ * Q' (bracketed by the roots of Q'', bisected to full FP64 precision), kept
+ * when it passes the sufficient-decrease test of Algorithm 4 with constant c.
+ * trials_out (device int32, may be NULL): 0, or -1 (alpha_out = 0) when
+ * coeffs[1] >= 0, Q has no minimiser on alpha > 0, or the test fails.
+ */
+ALS_API int ncg_linesearch_exact(als_ctx *ctx, const double *coeffs, double c, double *alpha_out,
+                                 int32_t *trials_out, void *stream);
+
+/*
  * Backtracking line search, Algorithm 4, evaluated on the device from the
  * quartic coefficients (no data pass): alpha = alpha0 tau^n for the first
  * n = 0, 1, ..., max_trials-1 with
@@ -274,7 +286,9 @@ ALS_API int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int l
  * restart and ALS-point safeguards, on the flat vectors x, p of Eq. (5)
  * ([U; M] with U = x, M = x + R->n_rows * ld):
  *   1. C = coefficients of f(x + alpha p) (one pass, as linesearch_coeffs);
- *      alpha by backtracking (alpha0, tau, c, max_trials as ncg_backtrack);
+ *      alpha by backtracking (search = 0: alpha0, tau, c, max_trials as
+ *      ncg_backtrack) or by the exact minimiser (search = 1: as
+ *      ncg_linesearch_exact; alpha0, tau, max_trials unused);
  *   2. if C1 >= 0 or no trial passed: p = -gbar and step 1 again (restart);
  *   3. if that fails too: the ALS point x = x - gbar (= x + p) is taken
  *      (safeguard; the next direction must restart), else x = x + alpha p.
@@ -291,8 +305,8 @@ ALS_API int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int l
  */
 ALS_API int ncg_linesearch_step(als_ctx *ctx, const als_plan *plan_R, const als_csr *R,
                                 const als_csr *Rt, void *x, void *p, const void *gbar, int n_f,
-                                int ld, double lambda, als_dtype dt, double alpha0, double tau,
-                                double c, int max_trials, double *state, void *stream);
+                                int ld, double lambda, als_dtype dt, int search, double alpha0,
+                                double tau, double c, int max_trials, double *state, void *stream);
 
 /*
  * ncg_direction with the restart decided on the device: beta = 0 when

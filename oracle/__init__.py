@@ -249,6 +249,37 @@ def backtrack(C, alpha0: float = ALPHA0, tau: float = TAU, c: float = C_ARMIJO,
     return None, max_trials
 
 
+# sufficient-decrease tolerance of the paper's serial line search (Section IV)
+C_EXACT = 1e-4
+
+
+def quartic_min(C, c: float = C_EXACT):
+    """Exact line search on the same quartic (the stronger search the paper's
+    serial runs use, Section IV, here on the Section V-C polynomial): the
+    global minimiser over alpha > 0 of Q(alpha) = sum C[n] alpha^n, from the
+    real roots of Q'(alpha) = C1 + 2 C2 alpha + 3 C3 alpha^2 + 4 C4 alpha^3
+    (numpy.roots).  Returned only when it also passes the sufficient-decrease
+    test of Algorithm 4 (divided by alpha, as in backtrack); else None.  None
+    when C1 >= 0 (not a descent direction) or Q has no minimiser on alpha > 0."""
+    C = [float(x) for x in C]
+    if not C[1] < 0.0:
+        return None
+    der = [4.0 * C[4], 3.0 * C[3], 2.0 * C[2], C[1]]
+    while der and der[0] == 0.0:
+        der = der[1:]
+    if len(der) < 2:
+        return None
+    roots = np.roots(der)
+    cand = [r.real for r in roots if abs(r.imag) <= 1e-12 * max(1.0, abs(r.real)) and r.real > 0.0]
+    if not cand:
+        return None
+    q = lambda a: C[0] + a * (C[1] + a * (C[2] + a * (C[3] + a * C[4])))  # noqa: E731
+    best = min(cand, key=q)
+    if (1.0 - c) * C[1] + best * (C[2] + best * (C[3] + best * C[4])) > 0.0:
+        return None
+    return best
+
+
 # ----------------------------------------------------------------------------
 # Algorithm 2 with pluggable pieces
 # ----------------------------------------------------------------------------

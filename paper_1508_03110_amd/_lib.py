@@ -63,8 +63,9 @@ _SIGS = {
     "ncg_axpy": (_i, [_vp, _i64, _vp, _vp, _vp, _i, _vp]),
     "ncg_axpby": (_i, [_vp, _i64, _d, _vp, _d, _vp, _i, _vp]),
     "ncg_direction": (_i, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp]),
-    "ncg_linesearch_step": (_i, [_vp, _vp, _csrp, _csrp, _vp, _vp, _vp, _i, _i, _d, _i, _d, _d, _d,
-                                 _i, _vp, _vp]),
+    "ncg_linesearch_step": (_i, [_vp, _vp, _csrp, _csrp, _vp, _vp, _vp, _i, _i, _d, _i, _i, _d, _d,
+                                 _d, _i, _vp, _vp]),
+    "ncg_linesearch_exact": (_i, [_vp, _vp, _d, _vp, _vp, _vp]),
     "ncg_direction_dev": (_i, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
     "fold_in": (_i, [_vp, _vp, _i64, _i, _i, _d, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "als_server_create": (_i, [_vp, _vp, _i64, _i, _i, _d, _i, ctypes.POINTER(ServerConfig),
@@ -227,12 +228,17 @@ def ncg_direction(ctx, n, x, xbar, g_new, g_old, p, scal, restart, pr_plus, dt, 
                                                         _stream(stream)))
 
 
-def ncg_linesearch_step(ctx, plan_R, R: Csr, Rt: Csr, x, p, gbar, n_f, ld, lam, dt, alpha0, tau, c,
-                        max_trials, state, stream=None):
+def ncg_linesearch_step(ctx, plan_R, R: Csr, Rt: Csr, x, p, gbar, n_f, ld, lam, dt, search, alpha0,
+                        tau, c, max_trials, state, stream=None):
     return _check("ncg_linesearch_step", load().ncg_linesearch_step(
         ctx, plan_R, ctypes.byref(R), ctypes.byref(Rt), _ptr(x), _ptr(p), _ptr(gbar), int(n_f),
-        int(ld), float(lam), int(dt), float(alpha0), float(tau), float(c), int(max_trials),
-        _ptr(state), _stream(stream)))
+        int(ld), float(lam), int(dt), int(search), float(alpha0), float(tau), float(c),
+        int(max_trials), _ptr(state), _stream(stream)))
+
+
+def ncg_linesearch_exact(ctx, coeffs, c, alpha_out, trials_out=None, stream=None):
+    return _check("ncg_linesearch_exact", load().ncg_linesearch_exact(
+        ctx, _ptr(coeffs), float(c), _ptr(alpha_out), _ptr(trials_out), _stream(stream)))
 
 
 def ncg_direction_dev(ctx, n, x, xbar, g_new, g_old, p, scal, restart_flag, pr_plus, dt, stream=None):

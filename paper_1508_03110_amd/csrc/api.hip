@@ -323,6 +323,13 @@ int ncg_backtrack(als_ctx *ctx, const double *coeffs, double alpha0, double tau,
                             (hipStream_t)stream);
 }
 
+int ncg_linesearch_exact(als_ctx *ctx, const double *coeffs, double c, double *alpha_out,
+                         int32_t *trials_out, void *stream) {
+    if (!ctx || !coeffs || !alpha_out || !(c > 0.0 && c < 1.0)) return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_quartic_min(coeffs, c, alpha_out, trials_out, (hipStream_t)stream);
+}
+
 int ncg_axpy(als_ctx *ctx, int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,
              void *stream) {
     if (!ctx || n < 0 || (n > 0 && (!x || !p)) || !alpha) return ALS_E_INVAL;
@@ -363,8 +370,9 @@ int ncg_direction_dev(als_ctx *ctx, int64_t n, const void *x, void *xbar, const 
 
 int ncg_linesearch_step(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, const als_csr *Rt,
                         void *x, void *p, const void *gbar, int n_f, int ld, double lambda,
-                        als_dtype dt, double alpha0, double tau, double c, int max_trials,
-                        double *state, void *stream) {
+                        als_dtype dt, int search, double alpha0, double tau, double c,
+                        int max_trials, double *state, void *stream) {
+    if (search != 0 && search != 1) return ALS_E_INVAL;
     if (!ctx || !csr_ok(R) || !Rt || !Rt->indptr || !plan_matches(plan_R, R) || !x || !p ||
         !gbar || !state || ld < n_f || !lambda_ok(lambda) || !dtype_ok(dt, n_f, false))
         return ALS_E_INVAL;
@@ -379,12 +387,12 @@ int ncg_linesearch_step(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, 
     char *xM = xU + (size_t)n_u * ld * elt, *pM = pU + (size_t)n_u * ld * elt;
     int rc = launch_coeffs(ctx, plan_R, R, Rt, xU, xM, pU, pM, n_f, ld, lambda, dt, state,
                            nullptr, s);
-    if (rc == ALS_OK) rc = launch_ls_first(state, alpha0, tau, c, max_trials, s);
+    if (rc == ALS_OK) rc = launch_ls_first(state, search, alpha0, tau, c, max_trials, s);
     if (rc == ALS_OK) rc = launch_ls_restart_dir(n, p, gbar, state, dt, s);
     if (rc == ALS_OK)
         rc = launch_coeffs(ctx, plan_R, R, Rt, xU, xM, pU, pM, n_f, ld, lambda, dt, state + 8,
                            state + 7, s);
-    if (rc == ALS_OK) rc = launch_ls_final(state, alpha0, tau, c, max_trials, s);
+    if (rc == ALS_OK) rc = launch_ls_final(state, search, alpha0, tau, c, max_trials, s);
     if (rc == ALS_OK) rc = launch_axpy(n, x, p, state + 21, dt, s);
     return rc;
 }

@@ -162,12 +162,14 @@ int launch_direction(Ctx *ctx, int64_t n, const void *x, void *xbar, const void 
 // Device-side line-search control (Algorithm 4 with the safeguards), see
 // ncg_linesearch_step in the header for the state layout.
 constexpr int kLsState = 32;
-int launch_ls_first(double *state, double alpha0, double tau, double c, int max_trials,
+int launch_ls_first(double *state, int exact, double alpha0, double tau, double c, int max_trials,
                     hipStream_t s);
 int launch_ls_restart_dir(int64_t n, void *p, const void *gbar, const double *state, als_dtype dt,
                           hipStream_t s);
-int launch_ls_final(double *state, double alpha0, double tau, double c, int max_trials,
+int launch_ls_final(double *state, int exact, double alpha0, double tau, double c, int max_trials,
                     hipStream_t s);
+int launch_quartic_min(const double *coeffs, double c, double *alpha_out, int32_t *trials_out,
+                       hipStream_t s);
 
 // Deterministic FP64 column sums of a row-major [rows, cols] array, cols <= 8
 // (two launches, fixed order).  out[k] = sum_r parts[r * cols + k] (+ out[k]

@@ -186,6 +186,94 @@ __device__ void backtrack_search(const double *C, double alpha0, double tau, dou
     *n_out = n;
 }
 
+// Exact line search on the same quartic: the global minimiser over alpha > 0
+// of Q(alpha) = sum C[n] alpha^n.  The real roots of Q'(alpha) = C1 + 2 C2 a
+// + 3 C3 a^2 + 4 C4 a^3 on (0, B] (B a Cauchy bound) are bracketed between
+// the roots of Q'' and found by bisection to full precision; the root with
+// the smallest Q is kept if it passes the divided Armijo test.  alpha = 0,
+// n = -1 when C1 >= 0, when Q has no minimiser on alpha > 0, or when the test
+// fails; else n = 0.
+__device__ void quartic_min_search(const double *C, double c, double *alpha_out, int *n_out) {
+#pragma clang fp contract(off)
+    const double c1 = C[1], c2 = C[2], c3 = C[3], c4 = C[4];
+    *alpha_out = 0.0;
+    *n_out = -1;
+    if (!(c1 < 0.0)) return;
+    // Q'(a) = d0 + d1 a + d2 a^2 + d3 a^3
+    const double d0 = c1, d1 = 2.0 * c2, d2 = 3.0 * c3, d3 = 4.0 * c4;
+    double lead;
+    int deg;
+    if (d3 != 0.0) {
+        deg = 3;
+        lead = d3;
+    } else if (d2 != 0.0) {
+        deg = 2;
+        lead = d2;
+    } else if (d1 != 0.0) {
+        deg = 1;
+        lead = d1;
+    } else {
+        return;  // Q' = C1 < 0 everywhere: no minimiser
+    }
+    if (!(lead > 0.0)) return;  // Q' -> -inf: Q unbounded below along p
+    const double B = 1.0 + fmax(fabs(d0 / lead), fmax(fabs(d1 / lead), fabs(d2 / lead)));
+    auto dq = [&](double a) { return d0 + a * (d1 + a * (d2 + a * d3)); };
+    auto q = [&](double a) { return C[0] + a * (c1 + a * (c2 + a * (c3 + a * c4))); };
+    // breakpoints: positive roots of Q''(a) = d1 + 2 d2 a + 3 d3 a^2 below B
+    double bp[4];
+    int nb = 0;
+    bp[nb++] = 0.0;
+    if (deg == 3) {
+        const double A2 = 3.0 * d3, A1 = 2.0 * d2, A0 = d1;
+        const double disc = A1 * A1 - 4.0 * A2 * A0;
+        if (disc >= 0.0) {
+            const double sq = sqrt(disc);
+            double r0 = (-A1 - sq) / (2.0 * A2), r1 = (-A1 + sq) / (2.0 * A2);
+            if (r0 > r1) { const double t = r0; r0 = r1; r1 = t; }
+            if (r0 > 0.0 && r0 < B) bp[nb++] = r0;
+            if (r1 > 0.0 && r1 < B) bp[nb++] = r1;
+        }
+    } else if (deg == 2) {
+        const double r = -d1 / (2.0 * d2);
+        if (r > 0.0 && r < B) bp[nb++] = r;
+    }
+    bp[nb++] = B;
+    double best = 0.0, qbest = 0.0;
+    bool found = false;
+    for (int k = 0; k + 1 < nb; ++k) {
+        double lo = bp[k], hi = bp[k + 1];
+        const double flo = dq(lo), fhi = dq(hi);
+        if (!(flo < 0.0 && fhi >= 0.0)) continue;  // a minimum of Q lies where Q' crosses upward
+        for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (dq(mid) < 0.0) lo = mid; else hi = mid;
+        }
+        const double a = hi;
+        const double qa = q(a);
+        if (!found || qa < qbest) {
+            best = a;
+            qbest = qa;
+            found = true;
+        }
+    }
+    if (!found) return;
+    const double test = (1.0 - c) * c1 + best * (c2 + best * (c3 + best * c4));
+    if (test <= 0.0) {
+        *alpha_out = best;
+        *n_out = 0;
+    }
+}
+
+__global__ void quartic_min_kernel(const double *__restrict__ C, double c,
+                                   double *__restrict__ alpha_out, int32_t *__restrict__ trials_out) {
+    double a;
+    int n;
+    quartic_min_search(C, c, &a, &n);
+    *alpha_out = a;
+    if (trials_out) *trials_out = n;
+}
+
 __global__ void backtrack_kernel(const double *__restrict__ C, double alpha0, double tau, double c,
                                  int max_trials, double *__restrict__ alpha_out,
                                  int32_t *__restrict__ trials_out) {
@@ -205,11 +293,19 @@ __global__ void backtrack_kernel(const double *__restrict__ C, double alpha0, do
 // [25] f(x_{k+1}) = Q(alpha) (NaN after a safeguard step), [26] total
 // restarts, [27] total safeguards, [28] iterations.
 
-__global__ void ls_first_kernel(double *__restrict__ st, double alpha0, double tau, double c,
-                                int max_trials) {
+__device__ void line_search(int exact, const double *C, double alpha0, double tau, double c,
+                            int max_trials, double *a, int *n) {
+    if (exact)
+        quartic_min_search(C, c, a, n);
+    else
+        backtrack_search(C, alpha0, tau, c, max_trials, a, n);
+}
+
+__global__ void ls_first_kernel(double *__restrict__ st, int exact, double alpha0, double tau,
+                                double c, int max_trials) {
     double a;
     int n;
-    backtrack_search(st, alpha0, tau, c, max_trials, &a, &n);
+    line_search(exact, st, alpha0, tau, c, max_trials, &a, &n);
     st[5] = a;
     st[6] = (double)n;
     st[7] = (st[1] >= 0.0 || n < 0) ? 1.0 : 0.0;
@@ -225,8 +321,8 @@ __global__ __launch_bounds__(kVecThreads) void ls_restart_dir_kernel(int64_t n, 
         p[i] = (T)(-(double)gbar[i]);
 }
 
-__global__ void ls_final_kernel(double *__restrict__ st, double alpha0, double tau, double c,
-                                int max_trials) {
+__global__ void ls_final_kernel(double *__restrict__ st, int exact, double alpha0, double tau,
+                                double c, int max_trials) {
 #pragma clang fp contract(off)
     const bool restarted = st[7] != 0.0;
     const double *C = st;
@@ -234,7 +330,7 @@ __global__ void ls_final_kernel(double *__restrict__ st, double alpha0, double t
     int n = (int)st[6];
     bool safe = false;
     if (restarted) {
-        backtrack_search(st + 8, alpha0, tau, c, max_trials, &alpha, &n);
+        line_search(exact, st + 8, alpha0, tau, c, max_trials, &alpha, &n);
         st[13] = alpha;
         st[14] = (double)n;
         C = st + 8;
@@ -260,6 +356,12 @@ void launch_sum_columns(const double *parts, int64_t rows, int cols, double *out
                        cols, stage);
     hipLaunchKernelGGL(sum_columns_stage2, dim3(1), dim3(kSumThreads), 0, s, stage, kSumBlocks,
                        cols, out, accumulate);
+}
+
+int launch_quartic_min(const double *coeffs, double c, double *alpha_out, int32_t *trials_out,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(quartic_min_kernel, dim3(1), dim3(1), 0, s, coeffs, c, alpha_out, trials_out);
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
 int launch_backtrack(const double *coeffs, double alpha0, double tau, double c, int max_trials,
@@ -302,15 +404,17 @@ int launch_axpby(int64_t n, double a, const void *x, double b, void *y, als_dtyp
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
-int launch_ls_first(double *state, double alpha0, double tau, double c, int max_trials,
+int launch_ls_first(double *state, int exact, double alpha0, double tau, double c, int max_trials,
                     hipStream_t s) {
-    hipLaunchKernelGGL(ls_first_kernel, dim3(1), dim3(1), 0, s, state, alpha0, tau, c, max_trials);
+    hipLaunchKernelGGL(ls_first_kernel, dim3(1), dim3(1), 0, s, state, exact, alpha0, tau, c,
+                       max_trials);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
-int launch_ls_final(double *state, double alpha0, double tau, double c, int max_trials,
+int launch_ls_final(double *state, int exact, double alpha0, double tau, double c, int max_trials,
                     hipStream_t s) {
-    hipLaunchKernelGGL(ls_final_kernel, dim3(1), dim3(1), 0, s, state, alpha0, tau, c, max_trials);
+    hipLaunchKernelGGL(ls_final_kernel, dim3(1), dim3(1), 0, s, state, exact, alpha0, tau, c,
+                       max_trials);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 

@@ -16,6 +16,10 @@ import torch
 from . import _lib as L
 
 TAU, C_ARMIJO, ALPHA0, MAX_TRIALS = 0.9, 0.5, 10.0, 400  # Section V-C
+# sufficient-decrease constant of the exact search: the tolerance of the
+# paper's serial line search (Section IV); with c = 0.5 the exact minimiser of
+# a nearly quadratic Q would sit on the boundary of the test
+C_EXACT = 1e-4
 
 # layout of the per-solver FP64 scalar block on the device
 S_DEN, S_BETA, S_GG, S_NUM = 0, 1, 2, 3
@@ -218,7 +222,8 @@ class Als:
 
 class AlsNcg:
     """Algorithm 2 (ALS-NCG) with the preconditioned beta of Eq. (8) and the
-    one-pass quartic backtracking line search of Section V-C.
+    one-pass quartic backtracking line search of Section V-C (search="exact":
+    the exact minimiser of the same quartic instead).
 
     Safeguards (the paper is silent on failures): a direction with
     g^T p >= 0 is reset to -gbar; if the line search still fails, the ALS
@@ -227,8 +232,14 @@ class AlsNcg:
 
     def __init__(self, prob: DeviceProblem, safeguard: bool = True, pr_plus: bool = False,
                  alpha0: float = ALPHA0, tau: float = TAU, c: float = C_ARMIJO,
-                 max_trials: int = MAX_TRIALS, precision: str = "fp", refine: bool = True):
+                 max_trials: int = MAX_TRIALS, precision: str = "fp", refine: bool = True,
+                 search: str = "backtracking"):
         _check_precision(prob, precision)
+        if search not in ("backtracking", "exact"):
+            raise ValueError("search must be 'backtracking' (Algorithm 4) or 'exact'")
+        self.search = search
+        if search == "exact" and c == C_ARMIJO:
+            c = C_EXACT
         self.p = prob
         self.precision, self.refine = precision, refine
         if precision == "bf16":
@@ -323,8 +334,12 @@ class AlsNcg:
         t = self._mark("linesearch_coeffs")
         P.coeffs(P.U(self.x), P.M(self.x), P.U(self.pdir), P.M(self.pdir), coef)
         self._done(t)
-        L.ncg_backtrack(P.ctx.handle, coef, self.alpha0, self.tau, self.c, self.max_trials,
-                        self.scal[S_ALPHA:S_ALPHA + 1], self.trials)
+        if self.search == "exact":
+            L.ncg_linesearch_exact(P.ctx.handle, coef, self.c, self.scal[S_ALPHA:S_ALPHA + 1],
+                                   self.trials)
+        else:
+            L.ncg_backtrack(P.ctx.handle, coef, self.alpha0, self.tau, self.c, self.max_trials,
+                            self.scal[S_ALPHA:S_ALPHA + 1], self.trials)
         host = self.scal.cpu().numpy()
         n = int(self.trials.cpu().item())
         C = host[S_COEF:S_COEF + 5].copy()
@@ -374,7 +389,8 @@ class AlsNcg:
         P = self.p
         t = self._mark("linesearch")
         L.ncg_linesearch_step(P.ctx.handle, P.R.plan, P.R.csr, P.Rt.csr, self.x, self.pdir,
-                              self.xbar, P.n_f, P.ld, P.lam, P.dt, self.alpha0, self.tau, self.c,
+                              self.xbar, P.n_f, P.ld, P.lam, P.dt,
+                              1 if self.search == "exact" else 0, self.alpha0, self.tau, self.c,
                               self.max_trials, self.state)
         self._done(t)
         self._precondition_and_gradient()

@@ -372,6 +372,57 @@ def test_als_ncg_20_iterations_lockstep(ctx, c0, dtype, tol):
     assert gpu.f < fa[-1]  # ALS-NCG ahead of ALS after the same number of iterations
 
 
+def test_exact_quartic_minimiser_matches_oracle(ctx):
+    """ncg_linesearch_exact against oracle.quartic_min (numpy's polynomial
+    roots) on random quartics, double wells, a vanishing quartic term and an
+    ascent direction."""
+    from paper_1508_03110_amd import _lib as L
+    rng = np.random.default_rng(17)
+    cases = []
+    for _ in range(300):
+        C = rng.normal(size=5) * 10.0 ** rng.integers(-3, 4, 5)
+        C[1] = -abs(C[1])
+        C[4] = abs(C[4])
+        cases.append(C)
+    cases += [np.array([1.0, -2.0, 1.0, 0.0, 0.0]), np.array([5.0, -1.0, -3.0, 0.5, 0.3]),
+              np.array([1.0, 0.5, 1.0, 0.0, 1.0]), np.array([1.0, -1.0, -1.0, -1.0, 0.0])]
+    dev = ctx.torch_device
+    for C in cases:
+        cd = torch.as_tensor(C, dtype=torch.float64, device=dev)
+        a = torch.zeros(1, dtype=torch.float64, device=dev)
+        n = torch.zeros(1, dtype=torch.int32, device=dev)
+        L.ncg_linesearch_exact(ctx.handle, cd, 1e-4, a, n)
+        ref = oracle.quartic_min(C, c=1e-4)
+        if ref is None:
+            assert int(n.item()) == -1 and float(a.item()) == 0.0, C
+        else:
+            assert int(n.item()) == 0, C
+            assert float(a.item()) == pytest.approx(ref, rel=1e-10), C
+
+
+def test_als_ncg_exact_search_lockstep(ctx, c0):
+    """Algorithm 2 with the exact minimiser of the same quartic, FP64, 15
+    iterations in lockstep with the oracle using oracle.quartic_min: f(x_k)
+    within 1e-10 relative at every iteration."""
+    from paper_1508_03110_amd.solver import AlsNcg
+    DP = dev_problem(ctx, c0, torch.float64)
+    gpu = AlsNcg(DP, search="exact").init(c0.U0, c0.M0)
+    o = oracle.NcgOracle(c0.R, c0.Rt, c0.n_f, c0.lam)
+
+    def exact_ls(x, p):
+        C = o.coeffs(x, p)
+        a = oracle.quartic_min(C)
+        fnew = float("nan") if a is None else float(np.polyval(C[::-1], a))
+        return a, (0 if a is not None else -1), fnew, float(C[1])
+
+    s = o.init(c0.U0, c0.M0)
+    for k in range(15):
+        gpu.step()
+        oracle.ncg_step(s, o.P, o.grad, exact_ls)
+        assert gpu.f == pytest.approx(o.f(s.x), rel=1e-10), k
+    assert gpu.safeguards == 0
+
+
 # ---------------------------------------------------------------- device-side control, graphs
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -386,7 +437,7 @@ def test_device_controlled_step_matches_host_step(ctx, dtype):
     DP = dev_problem(ctx, P, dtype)
     U0 = P.U0 if dtype == torch.float64 else r32(P.U0)
     M0 = P.M0 if dtype == torch.float64 else r32(P.M0)
-    for kw in ({}, dict(alpha0=1e3, max_trials=60)):
+    for kw in ({}, dict(alpha0=1e3, max_trials=60), dict(search="exact")):
         a = AlsNcg(DP, **kw).init(U0, M0)
         b = AlsNcg(DP, **kw).init(U0, M0)
         for k in range(12):
@@ -400,7 +451,7 @@ def test_device_controlled_step_matches_host_step(ctx, dtype):
                 assert math.isnan(b.f)
             else:
                 assert a.f == b.f and a.n_trials == b.n_trials, (kw, k)
-        if kw:  # the FP64 oracle takes 7 restarts and 7 ALS points here
+        if "alpha0" in kw:  # the FP64 oracle takes 7 restarts and 7 ALS points here
             assert b.restarts > 0 and 0 < b.safeguards < 12
 
 

@@ -400,3 +400,24 @@ def test_mixed_refinement_error_identity():
         e0 = max(e0, np.abs(x0[i] - xs[i]).max())
         e1 = max(e1, np.abs(x1[i] - xs[i]).max())
     assert e0 > 1e-4 and e1 < 0.05 * e0
+
+
+def test_quartic_min_is_the_global_minimiser_on_a_dense_grid():
+    """The exact line search returns the global minimiser of Q over alpha > 0:
+    checked against dense evaluation of Q on [0, 3 alpha*] for random quartics
+    with C1 < 0 and C4 > 0 (including double-well shapes), and None for an
+    ascent direction."""
+    rng = np.random.default_rng(13)
+    for _ in range(200):
+        C = rng.normal(size=5)
+        C[1] = -abs(C[1]) - 0.1
+        C[4] = abs(C[4]) + 0.05
+        a = oracle.quartic_min(C, c=1e-4)
+        q = lambda t: np.polyval(C[::-1], t)  # noqa: E731
+        grid = np.linspace(0.0, 3.0 * (a or 10.0), 200001)
+        gmin = q(grid).min()
+        if a is None:
+            assert q(grid).min() > C[0] + 1e-4 * grid[np.argmin(q(grid))] * C[1] - 1e-12
+            continue
+        assert q(a) <= gmin + 1e-9 * (1.0 + abs(gmin))
+    assert oracle.quartic_min([1.0, 0.5, 1.0, 0.0, 1.0]) is None
