@@ -329,9 +329,9 @@ def c2_bench(ctx, steps=5, als_steps=3):
     del als
     torch.cuda.empty_cache()
     # ALS-NCG: one eager device-controlled step with phase events, then graphs
-    s = AlsNcg(DP).init(x0[: DP.n_u * DP.ld].view(DP.n_u, DP.ld)[:, :n_f],
-                        x0[DP.n_u * DP.ld:].view(DP.n_m, DP.ld)[:, :n_f])
-    del x0
+    x0_U = x0[: DP.n_u * DP.ld].view(DP.n_u, DP.ld)[:, :n_f]
+    x0_M = x0[DP.n_u * DP.ld:].view(DP.n_m, DP.ld)[:, :n_f]
+    s = AlsNcg(DP).init(x0_U, x0_M)
     s.enable_timing(True)
     s.step_device()
     phases = s.phase_ms()
@@ -352,9 +352,55 @@ def c2_bench(ctx, steps=5, als_steps=3):
     fU = sweep_flops(DP.R.nnz, DP.n_u, n_f)
     out["sweep_U_tflops_eager"] = fU / (phases["sweep_U"] * 1e-3) / 1e12
     log("C2:", out["als"], out["als_ncg"])
-    del s, DP, Rd, Rtd
+    del s
+    out["speedup_vs_gnorm"] = c2_speedup_curve(DP, x0_U, x0_M, ms_als, ms_ncg, log=log)
+    del DP, Rd, Rtd, x0, x0_U, x0_M
     torch.cuda.empty_cache()
     return out
+
+
+def c2_speedup_curve(DP, U0, M0, ms_als, ms_ncg, n_ncg=25, n_als=100, log=None):
+    """Speedup of ALS-NCG over ALS as a function of the normalised gradient
+    norm, by the paper's method (Section VI, Fig. 6): for each ALS-NCG
+    iteration k the moving average of (1/N)||g|| over iterations k-1, k is
+    taken, the number j of ALS iterations needed to reach an equal or lower
+    (1/N)||g|| is looked up, and the times j t_ALS and k t_NCG are compared,
+    with the measured average times per iteration."""
+    import torch
+
+    from paper_1508_03110_amd.solver import Als, AlsNcg
+    N = DP.n_f * (DP.n_u + DP.n_m)
+    t0 = time.perf_counter()
+    ncg = AlsNcg(DP).init(U0, M0)
+    g_ncg = []
+    for _ in range(n_ncg):
+        ncg.step_device()
+        g_ncg.append(ncg.gnorm() / N)
+    del ncg
+    torch.cuda.empty_cache()
+    als = Als(DP, DP.pack(U0, M0))
+    g_als = []
+    for _ in range(n_als):
+        als.sweep()
+        g_als.append(DP.loss_and_gnorm(als.x)[1] / N)
+    del als
+    rows = []
+    for k in range(2, n_ncg + 1):
+        level = 0.5 * (g_ncg[k - 1] + g_ncg[k - 2])
+        j = next((i + 1 for i, g in enumerate(g_als) if g <= level), None)
+        rows.append({"ncg_iteration": k, "gnorm_over_N": level, "als_iterations": j,
+                     "speedup": (j * ms_als) / (k * ms_ncg) if j else None,
+                     # ALS did not get there in n_als iterations: a lower bound
+                     "speedup_at_least": None if j else (n_als * ms_als) / (k * ms_ncg)})
+    if log:
+        log("C2 speedup curve (%.1f s):" % (time.perf_counter() - t0),
+            [(r["ncg_iteration"], "%.2e" % r["gnorm_over_N"], r["als_iterations"],
+              round(r["speedup"], 2) if r["speedup"] else ">%.2f" % r["speedup_at_least"])
+             for r in rows[::3]])
+    return {"method": "paper Section VI: 2-iteration moving average of the ALS-NCG gradient norm, "
+                      "ALS iterations to reach it, times from the measured ms per iteration",
+            "ms_per_als_iteration": ms_als, "ms_per_ncg_iteration": ms_ncg,
+            "als_gnorm_over_N": g_als, "ncg_gnorm_over_N": g_ncg, "curve": rows}
 
 
 def serve_bench(ctx, M_dev, P, rates=(10_000, 50_000, 200_000), duration=2.0, warm=0.5,
