@@ -70,12 +70,28 @@ __device__ inline double inv_sqrt(double d) {
     return y * (1.5 - 0.5 * d * y * y);
 }
 
-// Sum over the 16 lanes that share l / 16 (result in all 16 lanes).
+// Sum over the 16 lanes that share l / 16 (result in all 16 lanes), as the
+// butterfly v += v[l ^ 1], v[l ^ 2], v[l ^ 4], v[l ^ 8].
 template <typename T> __device__ inline T sum16(T v) {
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
     v += __shfl_xor(v, 4);
     v += __shfl_xor(v, 8);
+    return v;
+}
+// FP32: the same additions through DPP lane moves instead of LDS permutes.
+// quad_perm [1,0,3,2] and [2,3,0,1] are l ^ 1 and l ^ 2; after them every lane
+// of a quad holds the quad's sum, so row_half_mirror (l -> 7 - l within 8)
+// adds the same value as l ^ 4, and row_mirror (l -> 15 - l within 16) the
+// same value as l ^ 8.  Same pairs, same order: bit-identical results.
+template <int CTRL> __device__ inline float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <> __device__ inline float sum16<float>(float v) {
+    v += dpp_f32<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f32<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f32<0x141>(v);  // row_half_mirror
+    v += dpp_f32<0x140>(v);  // row_mirror
     return v;
 }
 // Sum over the 4 lanes that share l % 16 (result in all 4 lanes).
