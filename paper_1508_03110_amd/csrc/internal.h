@@ -94,11 +94,22 @@ template <> __device__ inline float sum16<float>(float v) {
     v += dpp_f32<0x140>(v);  // row_mirror
     return v;
 }
-// Sum over the 4 lanes that share l % 16 (result in all 4 lanes).
+// Sum over the 4 lanes that share l % 16 (result in all 4 lanes), as the
+// butterfly v += v[l ^ 16], v[l ^ 32].
 template <typename T> __device__ inline T sum4g(T v) {
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
     return v;
+}
+// FP32: the same additions through the lane-swap instructions.  With both
+// operands v, permlane16_swap returns the even rows of 16 lanes duplicated
+// and the odd rows duplicated, whose sum is v[l] + v[l ^ 16] in every lane;
+// permlane32_swap does the same for the two halves of the wave (l ^ 32).
+template <> __device__ inline float sum4g<float>(float v) {
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 template <typename T> __device__ inline T sum64(T v) { return sum4g(sum16(v)); }
 
