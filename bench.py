@@ -488,21 +488,26 @@ def main():
     log("plans: R", infoR, "R^T", infoRt)
     U0 = P.U0.astype(np.float32)
     M0 = P.M0.astype(np.float32)
+    # Every decision of an iteration (line search, restart, safeguard) is
+    # taken on the device, so the iterations are queued back to back with no
+    # host read in between; f and the step counters are read once at the end.
     solver = AlsNcg(DP).init(U0, M0)
     for _ in range(args.warmup):
-        solver.step()
+        solver.step_device()
+    solver.read_state()
     log("warmup done: f=%.10g alpha=%s trials=%d" % (solver.f, solver.alpha, solver.n_trials))
 
     solver.enable_timing(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for k in range(args.steps):
-        solver.step()
+        solver.step_device()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     elapsed = t2 - t1
     ms_step = elapsed / args.steps * 1e3
     phases = solver.phase_ms()
+    solver.read_state()
     log("timed %d steps: %.3f ms/step, phases %s, f=%.10g" % (args.steps, ms_step, phases, solver.f))
 
     fU = sweep_flops(P.nnz, P.n_u, P.n_f)
@@ -536,10 +541,12 @@ def main():
         "half_sweep_ratings_per_s": {"U": P.nnz / tU, "M": P.nnz / tM},
         "phase_ms": {k: round(v, 4) for k, v in phases.items()},
         "sweep_tflops": {"U": fU / tU / 1e12, "M": fM / tM / 1e12},
-        "pass_hbm_gbs": {"linesearch_coeffs": by_coef / (phases["linesearch_coeffs"] * 1e-3) / 1e9,
+        "pass_hbm_gbs": {"linesearch": by_coef / (phases["linesearch"] * 1e-3) / 1e9,
                          "gradient_M": by_grad / (phases["gradient_M"] * 1e-3) / 1e9},
         "roofline": roofline,
         "f": solver.f,
+        "restarts": solver.restarts,
+        "safeguards": solver.safeguards,
         "gnorm_over_N": solver.gnorm() / (P.n_f * (P.n_u + P.n_m)),
     }
     fs = load_fstar()

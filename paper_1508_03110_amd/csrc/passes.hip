@@ -4,10 +4,11 @@
 // Function Evaluation").
 //
 // Both walk the same row plan as the half-sweep: one wavefront per chunk,
-// lane l = 16 g + c handles rating t + g of each group of 4 and factor
-// columns c, c + 16, ... of it, so every gathered factor row is read as 16
-// consecutive words per quarter-wave.  Dot products are formed in the factor
-// type and reduced across the 16 lanes of a quarter-wave; everything that
+// L lanes per rating (L = 8 or 16), lane l = L g + c on rating t + g of each
+// group of 64 / L and on factor columns c, c + L, ... of it (in vectors of
+// VEC), so every gathered factor row is read as L consecutive vectors.  Dot
+// products are formed in the factor type and reduced across the L lanes of a
+// rating; everything that
 // enters f, ||g||^2 or the quartic coefficients is accumulated in FP64 and
 // stored as one partial per chunk (or per block), then summed in a fixed
 // order, so results are bitwise reproducible.
@@ -22,11 +23,16 @@ namespace {
 
 // ---------------------------------------------------------------- gathered rows
 //
-// Lane (g, c) of a wavefront handles rating t + g of each group of 4 and the
-// factor columns col(q) = (16 q + c) * VEC, ..., + VEC - 1 for q < NV: with
-// VEC = 4 a quarter-wave reads 256 contiguous bytes of a factor row per load
-// (FP32 rows whose length and stride are multiples of 4), with VEC = 1 it
-// reads 16 consecutive elements.
+// Lane (g, c) of a wavefront handles rating t + g of each group of 64 / L and
+// the factor columns col(q) = (L q + c) * VEC, ..., + VEC - 1 for q < NV: with
+// VEC = 4 the L lanes of a rating read 16 L contiguous bytes of a factor row
+// per load (FP32 rows whose length and stride are multiples of 4), with
+// VEC = 1 they read L consecutive elements.
+//
+// The VALU issue rate bounds these passes (a wavefront instruction takes 4
+// cycles of a 16-lane SIMD): L = 8 halves the cross-lane reduction steps and
+// the FP64 accumulation instructions per rating against L = 16, and puts
+// fewer padding columns in each dot product for n_f <= 8 L VEC.
 template <typename T, int VEC> struct Vec {
     typedef T type __attribute__((ext_vector_type(VEC)));
 };
@@ -51,28 +57,95 @@ __device__ __forceinline__ T vdot(typename Vec<T, VEC>::type a, typename Vec<T, 
     }
 }
 
-template <typename T, int VEC, int NV>
-__device__ __forceinline__ void load_row(typename Vec<T, VEC>::type (&v)[NV], const T *__restrict__ base,
-                                         int64_t j, int ld, int n_f, bool ok, int c) {
-    typedef typename Vec<T, VEC>::type V;
-    const T *row = base + j * ld;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const int col = (16 * q + c) * VEC;
-        v[q] = (ok && col < n_f) ? *(const V *)(row + col) : vzero<T, VEC>();
+template <typename T, int VEC>
+__device__ __forceinline__ T velem(typename Vec<T, VEC>::type v, int u) {
+    if constexpr (VEC == 1) {
+        return v;
+    } else {
+        return v[u];
     }
 }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <typename T, int VEC, int NV>
+template <typename T, int VEC, int NV, int L>
 __device__ __forceinline__ void store_row(const typename Vec<T, VEC>::type (&v)[NV], T *__restrict__ base,
                                           int64_t j, int ld, int n_f, int c) {
     typedef typename Vec<T, VEC>::type V;
     T *row = base + j * ld;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        const int col = (16 * q + c) * VEC;
+        const int col = (L * q + c) * VEC;
         if (col < n_f) *(V *)(row + col) = v[q];
     }
+}
+
+// Unconditional row loads for the inner loops.  For q < NV - 1 every
+// vector is inside the row (NV = ceil(n_f / (L VEC))); the last one is
+// clamped to the row's last vector when (L (NV - 1) + c) VEC >= n_f, so
+// every load reads data of the addressed row and no lane branches.  The
+// duplicated columns are cancelled by zeros in the row-side operand
+// (load_own), lanes past the end of a chunk address a row of the same chunk
+// and their results are discarded.
+template <int VEC, int NV, int L> struct Cols {
+    int last;     // element offset of this lane's last vector (clamped)
+    bool last_ok; // that vector holds real columns
+    __device__ Cols(int c, int n_f) {
+        const int col = (L * (NV - 1) + c) * VEC;
+        last_ok = col < n_f;
+        last = last_ok ? col : n_f - VEC;
+    }
+};
+
+template <typename T, int VEC, int NV, int L>
+__device__ __forceinline__ void gather_row(typename Vec<T, VEC>::type (&v)[NV], const T *__restrict__ base,
+                                           int64_t j, int ld, int c, const Cols<VEC, NV, L> &cl) {
+    typedef typename Vec<T, VEC>::type V;
+    const T *row = base + j * ld;
+#pragma unroll
+    for (int q = 0; q < NV - 1; ++q) v[q] = *(const V *)(row + (L * q + c) * VEC);
+    v[NV - 1] = *(const V *)(row + cl.last);
+}
+
+// Row-side operand: the same loads, columns past n_f set to zero.
+template <typename T, int VEC, int NV, int L>
+__device__ __forceinline__ void load_own(typename Vec<T, VEC>::type (&v)[NV], const T *__restrict__ base,
+                                         int64_t j, int ld, int c, const Cols<VEC, NV, L> &cl) {
+    gather_row<T, VEC, NV, L>(v, base, j, ld, c, cl);
+    if (!cl.last_ok) v[NV - 1] = vzero<T, VEC>();
+}
+
+// Minimum wavefronts per SIMD asked of the compiler for the chunk kernels:
+// 4 for the FP32 vector-of-4 instances with one workgroup per chunk (at most
+// 128 VGPRs, which they fit without spilling), no constraint for the others.
+template <typename T, int VEC, bool PERSIST>
+constexpr int kPassWaves = (sizeof(T) == 4 && VEC == 4 && !PERSIST) ? 4 : 1;
+
+// Sum over the L lanes of a rating (result in all of them).
+template <int L, typename T> __device__ __forceinline__ T sum_rating(T v) {
+    if constexpr (L == 16) {
+        return sum16(v);
+    } else {
+        static_assert(L == 8, "8 or 16 lanes per rating");
+        if constexpr (sizeof(T) == 4) {
+            // quad_perm [1,0,3,2], [2,3,0,1], then row_half_mirror (l -> 7 - l
+            // within 8): the l ^ 1, l ^ 2, l ^ 4 butterfly on quad sums
+            v += dpp_f32<0xB1>(v);
+            v += dpp_f32<0x4E>(v);
+            v += dpp_f32<0x141>(v);
+            return v;
+        } else {
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            return v;
+        }
+    }
+}
+// Sum over the 64 / L ratings of a group for equal column lane c.
+template <int L, typename T> __device__ __forceinline__ T sum_group(T v) {
+    if constexpr (L == 8) v += __shfl_xor(v, 8);
+    return sum4g(v);
 }
 
 // ---------------------------------------------------------------- gradient
@@ -84,8 +157,8 @@ __device__ __forceinline__ void store_row(const typename Vec<T, VEC>::type (&v)[
 // that are whole in this chunk); split rows leave the regulariser and ||G||^2
 // to grad_split_kernel.  Rating ids are fetched two groups ahead and factor
 // rows one group ahead of their use.
-template <typename T, int VEC, int NV, bool PERSIST>
-__global__ __launch_bounds__(64) void grad_chunks_kernel(
+template <typename T, int VEC, int NV, int L, bool PERSIST>
+__global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void grad_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ X, const T *__restrict__ Y, int n_f,
     int ld, double lambda, int64_t n_chunks, const int32_t *__restrict__ chunk_row,
@@ -93,54 +166,67 @@ __global__ __launch_bounds__(64) void grad_chunks_kernel(
     const int32_t *__restrict__ chunk_slot, T *__restrict__ G, T *__restrict__ partial,
     double *__restrict__ scal, int data_in_f, int want_g) {
     typedef typename Vec<T, VEC>::type V;
+    constexpr int GR = kWave / L;  // ratings per step
     const int64_t stride = PERSIST ? (int64_t)gridDim.x : n_chunks;
     for (int64_t q = blockIdx.x; q < n_chunks; q += stride) {
-    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x, g = lane / L, c = lane % L;
+    const Cols<VEC, NV, L> cl(c, n_f);
     const int64_t row = chunk_row[q], b = chunk_begin[q], e = b + chunk_len[q];
     const int slot = chunk_slot[q];
     V x[NV], acc[NV];
-    load_row<T, VEC, NV>(x, X, row, ld, n_f, true, c);
+    load_own<T, VEC, NV, L>(x, X, row, ld, c, cl);
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = vzero<T, VEC>();
     double e2 = 0.0;
     if (b < e) {
-        V cur[NV];
-        bool okc = b + g < e;
-        T rc = okc ? (T)val[b + g] : T(0);
-        load_row<T, VEC, NV>(cur, Y, okc ? idx[b + g] : 0, ld, n_f, okc, c);
-        bool ok1 = b + 4 + g < e;
-        int j1 = ok1 ? idx[b + 4 + g] : 0;
-        T r1 = ok1 ? (T)val[b + 4 + g] : T(0);
-        for (int64_t t = b; t < e; t += 4) {
-            V nxt[NV];
-            load_row<T, VEC, NV>(nxt, Y, j1, ld, n_f, ok1, c);
-            const bool ok2 = t + 8 + g < e;
-            const int j2 = ok2 ? idx[t + 8 + g] : 0;
-            const T r2 = ok2 ? (T)val[t + 8 + g] : T(0);
+        // rating t + g of a group: id (a row of this chunk past the end), value
+        const int jl = idx[e - 1];
+        auto rid = [&](int64_t t, bool &ok, T &r) -> int {
+            ok = t < e;
+            r = ok ? (T)val[t] : T(0);
+            return ok ? idx[t] : jl;
+        };
+        auto step = [&](const V (&y)[NV], bool ok, T r) {
             T d = T(0);
 #pragma unroll
-            for (int k = 0; k < NV; ++k) d += vdot<T, VEC>(x[k], cur[k]);
-            d = sum16(d);
-            const T res = okc ? d - rc : T(0);
+            for (int k = 0; k < NV; ++k) d += vdot<T, VEC>(x[k], y[k]);
+            d = sum_rating<L>(d);
+            const T res = ok ? d - r : T(0);
 #pragma unroll
-            for (int k = 0; k < NV; ++k) acc[k] += res * cur[k];
+            for (int k = 0; k < NV; ++k) acc[k] += res * y[k];
             if (c == 0) e2 += (double)res * (double)res;
-#pragma unroll
-            for (int k = 0; k < NV; ++k) cur[k] = nxt[k];
-            okc = ok1;
-            rc = r1;
-            ok1 = ok2;
-            j1 = j2;
-            r1 = r2;
+        };
+        // two buffers: group t in A, group t + GR in B (ids one group ahead)
+        V ya[NV], yb[NV];
+        bool oka, okb;
+        T ra, rb;
+        gather_row<T, VEC, NV, L>(ya, Y, rid(b + g, oka, ra), ld, c, cl);
+        int jb = rid(b + GR + g, okb, rb);
+        for (int64_t t = b; t < e; t += 2 * GR) {
+            gather_row<T, VEC, NV, L>(yb, Y, jb, ld, c, cl);
+            bool okn;
+            T rn;
+            const int jn = rid(t + 2 * GR + g, okn, rn);
+            step(ya, oka, ra);
+            gather_row<T, VEC, NV, L>(ya, Y, jn, ld, c, cl);
+            bool okm;
+            T rm;
+            jb = rid(t + 3 * GR + g, okm, rm);
+            step(yb, okb, rb);
+            oka = okn;
+            ra = rn;
+            okb = okm;
+            rb = rm;
         }
     }
+    if (!cl.last_ok) acc[NV - 1] = vzero<T, VEC>();  // duplicated columns
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         if constexpr (VEC == 1) {
-            acc[k] = sum4g(acc[k]);
+            acc[k] = sum_group<L>(acc[k]);
         } else {
 #pragma unroll
-            for (int u = 0; u < VEC; ++u) acc[k][u] = sum4g(acc[k][u]);
+            for (int u = 0; u < VEC; ++u) acc[k][u] = sum_group<L>(acc[k][u]);
         }
     }
     e2 = sum64(e2);
@@ -157,7 +243,7 @@ __global__ __launch_bounds__(64) void grad_chunks_kernel(
                 xn += (double)vdot<T, VEC>(x[k], x[k]);
             }
         }
-        if (G && g == 0) store_row<T, VEC, NV>(gv, G, row, ld, n_f, c);
+        if (G && g == 0) store_row<T, VEC, NV, L>(gv, G, row, ld, n_f, c);
         gn = sum64(gn);
         xn = sum64(xn);
         if (lane == 0) {
@@ -165,7 +251,7 @@ __global__ __launch_bounds__(64) void grad_chunks_kernel(
             scal[2 * q + 1] = want_g ? gn : 0.0;
         }
     } else {
-        if (g == 0) store_row<T, VEC, NV>(acc, partial, slot, NV * 16 * VEC, n_f, c);
+        if (g == 0) store_row<T, VEC, NV, L>(acc, partial, slot, NV * L * VEC, n_f, c);
         if (lane == 0) {
             scal[2 * q] = data_in_f ? e2 : 0.0;
             scal[2 * q + 1] = 0.0;
@@ -211,8 +297,8 @@ __global__ __launch_bounds__(64) void grad_split_kernel(
 //   (r - u.m)^2 = d^2 - 2 d a1 alpha + (a1^2 - 2 d a2) alpha^2 + 2 a1 a2 alpha^3 + a2^2 alpha^4.
 // The first chunk of each user row also adds that user's regulariser
 // lambda n_i ||xu + alpha pu||^2.  part[5q + n] is the chunk's share of C_n.
-template <typename T, int VEC, int NV, bool PERSIST>
-__global__ __launch_bounds__(64) void coeff_chunks_kernel(
+template <typename T, int VEC, int NV, int L, bool PERSIST>
+__global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void coeff_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ XU, const T *__restrict__ XM,
     const T *__restrict__ PU, const T *__restrict__ PM, int n_f, int ld, double lambda,
@@ -220,62 +306,78 @@ __global__ __launch_bounds__(64) void coeff_chunks_kernel(
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
     double *__restrict__ part, const double *__restrict__ pred) {
     typedef typename Vec<T, VEC>::type V;
+    constexpr int GR = kWave / L;  // ratings per step
     if (pred && *pred == 0.0) return;
     const int64_t stride = PERSIST ? (int64_t)gridDim.x : n_chunks;
     for (int64_t q = blockIdx.x; q < n_chunks; q += stride) {
-    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x, g = lane / L, c = lane % L;
+    const Cols<VEC, NV, L> cl(c, n_f);
     const int64_t row = chunk_row[q], b = chunk_begin[q], e = b + chunk_len[q];
     V xu[NV], pu[NV];
-    load_row<T, VEC, NV>(xu, XU, row, ld, n_f, true, c);
-    load_row<T, VEC, NV>(pu, PU, row, ld, n_f, true, c);
+    load_own<T, VEC, NV, L>(xu, XU, row, ld, c, cl);
+    load_own<T, VEC, NV, L>(pu, PU, row, ld, c, cl);
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
     if (b < e) {
-        V xc[NV], pc[NV];
-        bool okc = b + g < e;
-        float rc = okc ? val[b + g] : 0.0f;
-        {
-            const int j0 = okc ? idx[b + g] : 0;
-            load_row<T, VEC, NV>(xc, XM, j0, ld, n_f, okc, c);
-            load_row<T, VEC, NV>(pc, PM, j0, ld, n_f, okc, c);
-        }
-        bool ok1 = b + 4 + g < e;
-        int j1 = ok1 ? idx[b + 4 + g] : 0;
-        float r1 = ok1 ? val[b + 4 + g] : 0.0f;
-        for (int64_t t = b; t < e; t += 4) {
-            V xn[NV], pn[NV];
-            load_row<T, VEC, NV>(xn, XM, j1, ld, n_f, ok1, c);
-            load_row<T, VEC, NV>(pn, PM, j1, ld, n_f, ok1, c);
-            const bool ok2 = t + 8 + g < e;
-            const int j2 = ok2 ? idx[t + 8 + g] : 0;
-            const float r2 = ok2 ? val[t + 8 + g] : 0.0f;
+        // rating t + g of a group: id (a row of this chunk past the end), value
+        const int jl = idx[e - 1];
+        auto rid = [&](int64_t t, bool &ok, float &r) -> int {
+            ok = t < e;
+            r = ok ? val[t] : 0.0f;
+            return ok ? idx[t] : jl;
+        };
+        auto step = [&](const V (&xm)[NV], const V (&pm)[NV], bool ok, float r) {
+            // one FMA chain per dot product (a1 takes both of its terms)
             T a0 = T(0), a1 = T(0), a2 = T(0);
 #pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                a0 += vdot<T, VEC>(xu[k], xc[k]);
-                a1 += vdot<T, VEC>(xu[k], pc[k]) + vdot<T, VEC>(pu[k], xc[k]);
-                a2 += vdot<T, VEC>(pu[k], pc[k]);
-            }
-            a0 = sum16(a0);
-            a1 = sum16(a1);
-            a2 = sum16(a2);
-            if (okc && c == 0) {
-                const double d = (double)rc - (double)a0, A1 = (double)a1, A2 = (double)a2;
+            for (int k = 0; k < NV; ++k)
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) {
+                    const T xuk = velem<T, VEC>(xu[k], u), puk = velem<T, VEC>(pu[k], u);
+                    const T xmk = velem<T, VEC>(xm[k], u), pmk = velem<T, VEC>(pm[k], u);
+                    a0 = fma_t(xuk, xmk, a0);
+                    a1 = fma_t(xuk, pmk, a1);
+                    a1 = fma_t(puk, xmk, a1);
+                    a2 = fma_t(puk, pmk, a2);
+                }
+            a0 = sum_rating<L>(a0);
+            a1 = sum_rating<L>(a1);
+            a2 = sum_rating<L>(a2);
+            if (ok && c == 0) {
+                const double d = (double)r - (double)a0, A1 = (double)a1, A2 = (double)a2;
                 c0 += d * d;
                 c1 += -2.0 * d * A1;
                 c2 += A1 * A1 - 2.0 * d * A2;
                 c3 += 2.0 * A1 * A2;
                 c4 += A2 * A2;
             }
-#pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                xc[k] = xn[k];
-                pc[k] = pn[k];
-            }
-            okc = ok1;
-            rc = r1;
-            ok1 = ok2;
-            j1 = j2;
-            r1 = r2;
+        };
+        // two buffers: group t in A, group t + GR in B (ids one group ahead)
+        V xa[NV], pa[NV], xb[NV], pb[NV];
+        bool oka, okb;
+        float ra, rb;
+        {
+            const int j0 = rid(b + g, oka, ra);
+            gather_row<T, VEC, NV, L>(xa, XM, j0, ld, c, cl);
+            gather_row<T, VEC, NV, L>(pa, PM, j0, ld, c, cl);
+        }
+        int jb = rid(b + GR + g, okb, rb);
+        for (int64_t t = b; t < e; t += 2 * GR) {
+            gather_row<T, VEC, NV, L>(xb, XM, jb, ld, c, cl);
+            gather_row<T, VEC, NV, L>(pb, PM, jb, ld, c, cl);
+            bool okn;
+            float rn;
+            const int jn = rid(t + 2 * GR + g, okn, rn);
+            step(xa, pa, oka, ra);
+            gather_row<T, VEC, NV, L>(xa, XM, jn, ld, c, cl);
+            gather_row<T, VEC, NV, L>(pa, PM, jn, ld, c, cl);
+            bool okm;
+            float rm;
+            jb = rid(t + 3 * GR + g, okm, rm);
+            step(xb, pb, okb, rb);
+            oka = okn;
+            ra = rn;
+            okb = okm;
+            rb = rm;
         }
     }
     c0 = sum64(c0);
@@ -383,11 +485,12 @@ static unsigned chunk_grid(const Plan *p) {
     return (unsigned)(p->grid_pass > 0 ? std::min<int64_t>(p->grid_pass, p->n_chunks) : p->n_chunks);
 }
 
-template <typename T, int VEC, int NV>
+template <typename T, int VEC, int NV, int L>
 int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
                  const T *U, const T *M, int n_f, int ld, double lambda, T *gU, T *gM,
                  double *out2, hipStream_t s) {
-    constexpr int NP = NV * 16 * VEC;
+    constexpr int NP = NV * L * VEC;
+    if ((int64_t)L * (NV - 1) * VEC >= n_f || NP < n_f) return ALS_E_INVAL;  // see Cols
     const bool doR = (gU != nullptr) || (out2 != nullptr);
     const bool doRt = (gM != nullptr) || (out2 != nullptr);
     const int64_t rowsR = doR ? pR->n_chunks + pR->n_split_rows : 0;
@@ -405,7 +508,7 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
     if (doR) {
         if (pR->n_chunks) {
 #define ALS_GRAD_R(P)                                                                               \
-    hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV, P>), dim3(chunk_grid(pR)), dim3(kWave), 0, s, \
+    hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV, L, P>), dim3(chunk_grid(pR)), dim3(kWave), 0, s, \
                        R->indptr, R->indices, R->values, U, M, n_f, ld, lambda, pR->n_chunks,       \
                        pR->chunk_row, pR->chunk_begin, pR->chunk_len, pR->chunk_slot, gU, partR,    \
                        scal, 1, gU != nullptr ? 1 : 0)
@@ -425,7 +528,7 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
         double *sc = scal + 2 * rowsR;
         if (pRt->n_chunks) {
 #define ALS_GRAD_RT(P)                                                                               \
-    hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV, P>), dim3(chunk_grid(pRt)), dim3(kWave), 0, s, \
+    hipLaunchKernelGGL((grad_chunks_kernel<T, VEC, NV, L, P>), dim3(chunk_grid(pRt)), dim3(kWave), 0, s, \
                        Rt->indptr, Rt->indices, Rt->values, M, U, n_f, ld, lambda, pRt->n_chunks,    \
                        pRt->chunk_row, pRt->chunk_begin, pRt->chunk_len, pRt->chunk_slot, gM,        \
                        partRt, sc, 0, gM != nullptr ? 1 : 0)
@@ -447,10 +550,11 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
-template <typename T, int VEC, int NV>
+template <typename T, int VEC, int NV, int L>
 int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const T *U,
                const T *M, const T *PU, const T *PM, int n_f, int ld, double lambda,
                double *coeffs, const double *pred, hipStream_t s) {
+    if ((int64_t)L * (NV - 1) * VEC >= n_f || L * NV * VEC < n_f) return ALS_E_INVAL;  // see Cols
     const int64_t rows = pR->n_chunks + kItemBlocks;
     int err = ALS_OK;
     double *part =
@@ -465,7 +569,7 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
         if (pred && pR->grid_pass <= 0)
             grid = (unsigned)std::min<int64_t>(pR->n_chunks, (int64_t)ctx->num_cu * 16);
 #define ALS_COEF(P)                                                                             \
-    hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV, P>), dim3(grid), dim3(kWave), 0, s,       \
+    hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV, L, P>), dim3(grid), dim3(kWave), 0, s,       \
                        R->indptr, R->indices, R->values, U, M, PU, PM, n_f, ld, lambda,         \
                        pR->n_chunks, pR->chunk_row, pR->chunk_begin, pR->chunk_len, part, pred)
         if (persist)
@@ -474,26 +578,12 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
             ALS_COEF(false);
 #undef ALS_COEF
     }
-    hipLaunchKernelGGL((coeff_itemreg_kernel<T, NV * VEC>), dim3(kItemBlocks), dim3(256), 0, s,
+    hipLaunchKernelGGL((coeff_itemreg_kernel<T, (NV * L * VEC + 15) / 16>), dim3(kItemBlocks), dim3(256), 0, s,
                        Rt->indptr, Rt->n_rows, M, PM, n_f, ld, lambda, part + 5 * pR->n_chunks,
                        pred);
     launch_sum_columns(part, rows, 5, coeffs, 0, part + rows * 5, s);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
-
-#define ALS_NBV_SWITCH(nbv, CALL) \
-    switch (nbv) {                \
-        case 1: CALL(1);          \
-        case 2: CALL(2);          \
-        case 3: CALL(3);          \
-        case 4: CALL(4);          \
-        case 5: CALL(5);          \
-        case 6: CALL(6);          \
-        case 7: CALL(7);          \
-        case 8: CALL(8);          \
-        case 9: CALL(9);          \
-        default: return ALS_E_INVAL; \
-    }
 
 // FP32 rows of length and stride divisible by 4 on 16-byte boundaries are
 // gathered 4 elements per lane; everything else one element per lane.
@@ -506,52 +596,65 @@ static bool vec4_ok(int n_f, int ld, std::initializer_list<const void *> ptrs) {
 
 }  // namespace
 
+// Lanes per rating and vectors per lane for n_f: FP32 rows in vectors of 4
+// with 8 lanes per rating up to n_f = 128, else 16; single elements with 8
+// lanes up to n_f = 64, else 16.
+#define ALS_PASS_DISPATCH(dt, n_f, vec4, X)                            \
+    do {                                                               \
+        if ((dt) == ALS_F32 && (vec4)) {                               \
+            switch (((n_f) + 31) / 32) {                               \
+                case 1: X(float, 4, 1, 8);                             \
+                case 2: X(float, 4, 2, 8);                             \
+                case 3: X(float, 4, 3, 8);                             \
+                case 4: X(float, 4, 4, 8);                             \
+                case 5:                                                \
+                case 6: X(float, 4, 3, 16);                            \
+                default: return ALS_E_INVAL;                           \
+            }                                                          \
+        }                                                              \
+        if ((dt) != ALS_F32 && (dt) != ALS_F64) return ALS_E_INVAL;    \
+        if ((n_f) <= 64) {                                             \
+            switch (((n_f) + 7) / 8) {                                 \
+                case 1: ALS_PASS_T(dt, X, 1, 1, 8);                    \
+                case 2: ALS_PASS_T(dt, X, 1, 2, 8);                    \
+                case 3: ALS_PASS_T(dt, X, 1, 3, 8);                    \
+                case 4: ALS_PASS_T(dt, X, 1, 4, 8);                    \
+                case 5: ALS_PASS_T(dt, X, 1, 5, 8);                    \
+                case 6: ALS_PASS_T(dt, X, 1, 6, 8);                    \
+                case 7: ALS_PASS_T(dt, X, 1, 7, 8);                    \
+                default: ALS_PASS_T(dt, X, 1, 8, 8);                   \
+            }                                                          \
+        }                                                              \
+        switch (((n_f) + 15) / 16) {                                   \
+            case 5: ALS_PASS_T(dt, X, 1, 5, 16);                       \
+            case 6: ALS_PASS_T(dt, X, 1, 6, 16);                       \
+            case 7: ALS_PASS_T(dt, X, 1, 7, 16);                       \
+            case 8: ALS_PASS_T(dt, X, 1, 8, 16);                       \
+            case 9: ALS_PASS_T(dt, X, 1, 9, 16);                       \
+            default: return ALS_E_INVAL;                               \
+        }                                                              \
+    } while (0)
+#define ALS_PASS_T(dt, X, VEC, NV, L) \
+    if ((dt) == ALS_F32) X(float, VEC, NV, L); else X(double, VEC, NV, L)
+
 int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
                     const void *U, const void *M, int n_f, int ld, double lambda, als_dtype dt,
                     void *gU, void *gM, double *out2, hipStream_t s) {
-#define GA(T, VEC, NV) \
-    return run_gradient<T, VEC, NV>(ctx, pR, R, pRt, Rt, (const T *)U, (const T *)M, n_f, ld, lambda, (T *)gU, (T *)gM, out2, s)
-    if (dt == ALS_F32 && vec4_ok(n_f, ld, {U, M, gU, gM})) {
-        switch ((n_f + 63) / 64) {
-            case 1: GA(float, 4, 1);
-            case 2: GA(float, 4, 2);
-            case 3: GA(float, 4, 3);
-            default: return ALS_E_INVAL;
-        }
-    }
-#define G32(N) GA(float, 1, N)
-#define G64(N) GA(double, 1, N)
-    const int nbv = (n_f + 15) / 16;
-    if (dt == ALS_F32) { ALS_NBV_SWITCH(nbv, G32) }
-    if (dt == ALS_F64) { ALS_NBV_SWITCH(nbv, G64) }
-#undef G32
-#undef G64
+#define GA(T, VEC, NV, L)                                                                         \
+    return run_gradient<T, VEC, NV, L>(ctx, pR, R, pRt, Rt, (const T *)U, (const T *)M, n_f, ld, \
+                                       lambda, (T *)gU, (T *)gM, out2, s)
+    ALS_PASS_DISPATCH(dt, n_f, vec4_ok(n_f, ld, {U, M, gU, gM}), GA);
 #undef GA
-    return ALS_E_INVAL;
 }
 
 int launch_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const void *U,
                   const void *M, const void *pU, const void *pM, int n_f, int ld, double lambda,
                   als_dtype dt, double *coeffs, const double *pred, hipStream_t s) {
-#define CA(T, VEC, NV) \
-    return run_coeffs<T, VEC, NV>(ctx, pR, R, Rt, (const T *)U, (const T *)M, (const T *)pU, (const T *)pM, n_f, ld, lambda, coeffs, pred, s)
-    if (dt == ALS_F32 && vec4_ok(n_f, ld, {U, M, pU, pM})) {
-        switch ((n_f + 63) / 64) {
-            case 1: CA(float, 4, 1);
-            case 2: CA(float, 4, 2);
-            case 3: CA(float, 4, 3);
-            default: return ALS_E_INVAL;
-        }
-    }
-#define C32(N) CA(float, 1, N)
-#define C64(N) CA(double, 1, N)
-    const int nbv = (n_f + 15) / 16;
-    if (dt == ALS_F32) { ALS_NBV_SWITCH(nbv, C32) }
-    if (dt == ALS_F64) { ALS_NBV_SWITCH(nbv, C64) }
-#undef C32
-#undef C64
+#define CA(T, VEC, NV, L)                                                                       \
+    return run_coeffs<T, VEC, NV, L>(ctx, pR, R, Rt, (const T *)U, (const T *)M, (const T *)pU, \
+                                     (const T *)pM, n_f, ld, lambda, coeffs, pred, s)
+    ALS_PASS_DISPATCH(dt, n_f, vec4_ok(n_f, ld, {U, M, pU, pM}), CA);
 #undef CA
-    return ALS_E_INVAL;
 }
 
 }  // namespace alsncg
