@@ -59,17 +59,21 @@ template <int NB> struct Slots {
 // (j is 0 for ratings past the end of the chunk and columns past n_f are
 // clamped into the row) so that no branch or mask sits between a load and its
 // use; finish_operand() applies the masks when the MFMAs consume the values.
-// vec: the row may be read with 16- and 8-byte loads (FP32, 16-byte aligned).
-template <typename T, int NB>
+// VEC: the row is read with 16- and 8-byte loads (FP32, 16-byte aligned
+// rows).  It is a template parameter: a run-time choice puts a branch around
+// every load, and across such branches the compiler waits for all loads in
+// flight right after issuing one, which serialises the gather pipeline.
+template <typename T, int NB, bool VEC>
 __device__ __forceinline__ void gather_row(T (&gv)[NB], const T *__restrict__ Y, int j, int ld,
-                                           int n_f, int c, bool vec) {
+                                           int n_f, int c) {
     typedef Slots<NB> SL;
     const T *row = Y + (int64_t)j * ld;
 #pragma unroll
     for (int q = 0; q < SL::Q; ++q) {
         const T *p4 = row + 64 * q + 4 * c;
-        if constexpr (sizeof(T) == 4) {
-            if (vec) {
+        if constexpr (VEC) {
+            static_assert(sizeof(T) == 4, "vector loads of FP32 rows");
+            {
                 typedef float f4 __attribute__((ext_vector_type(4)));
                 const f4 v = *(const f4 *)p4;
 #pragma unroll
@@ -82,17 +86,12 @@ __device__ __forceinline__ void gather_row(T (&gv)[NB], const T *__restrict__ Y,
     }
     if constexpr (SL::P == 1) {
         const T *p2 = row + 64 * SL::Q + 2 * c;
-        bool done = false;
-        if constexpr (sizeof(T) == 4) {
-            if (vec) {
-                typedef float f2 __attribute__((ext_vector_type(2)));
-                const f2 v = *(const f2 *)p2;
-                gv[4 * SL::Q] = v[0];
-                gv[4 * SL::Q + 1] = v[1];
-                done = true;
-            }
-        }
-        if (!done) {
+        if constexpr (VEC) {
+            typedef float f2 __attribute__((ext_vector_type(2)));
+            const f2 v = *(const f2 *)p2;
+            gv[4 * SL::Q] = v[0];
+            gv[4 * SL::Q + 1] = v[1];
+        } else {
             gv[4 * SL::Q] = p2[0];
             gv[4 * SL::Q + 1] = p2[1];
         }
@@ -130,51 +129,69 @@ __device__ __forceinline__ void gram_update(typename Mfma<T>::acc4 (&A)[Tri<NB>:
             A[Tri<NB>::id(a, bb)] = Mfma<T>::mma(gv[a], gv[bb], A[Tri<NB>::id(a, bb)]);
 }
 
-// Gram accumulation over ratings [b, e) of one row.  Two register buffers
-// alternate: while the MFMAs consume group s, the factor rows of group s + 1
-// and the rating id of group s + 2 are in flight.  The loop body covers two
-// groups so that no register is copied between a load and its use (a copy
-// would force the wait for the load right after issuing it), and has a single
-// exit (exits in the middle make the allocator duplicate the accumulators).
+// Gram accumulation over ratings [b, e) of one row.  kGramDepth register
+// buffers rotate: while the MFMAs consume group s, the factor rows of groups
+// s + 1 .. s + kGramDepth - 1 are in flight.  The gather of a group comes
+// from L2, the Infinity Cache or HBM and takes several times as long as its
+// 4 ratings' MFMAs, so one group in flight per wavefront leaves the matrix
+// cores idle most of the time.
+//
+// Loads complete in issue order as far as the wait counter is concerned:
+// waiting for one load waits for every load issued before it.  The rating
+// ids (and values) of a group are therefore loaded kGramDepth steps before
+// its gather is issued (a ring of ids), so that waiting for an id only
+// waits for gathers of groups already consumed, never for those in flight.
+// The loop body covers kGramDepth groups with every buffer and ring index
+// fixed in each copy, so no register is copied between a load and its use,
+// and has a single exit (exits in the middle make the allocator duplicate
+// the accumulators); groups past the end are skipped by a uniform branch.
 // Loads for groups past the end read valid addresses and are discarded.
-template <typename T, int NB>
+constexpr int kGramDepth = 4;
+
+template <typename T, int NB, bool VEC>
 __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
                                                 const int32_t *__restrict__ idx,
                                                 const float *__restrict__ val, int64_t b, int64_t e,
                                                 const T *__restrict__ Y, int ld, int n_f, int g,
-                                                int c, bool vec) {
+                                                int c) {
+    constexpr int D = kGramDepth;
     if (b >= e) return;
     const int last = (int)(e - 1 - b);
     const int ng = (last >> 2) + 1;
     const int32_t *ix = idx + b;
     const float *vx = val + b;
-    T buf0[NB], buf1[NB];
-    int p = min(g, last);
-    float r0 = vx[p];
-    gather_row<T, NB>(buf0, Y, ix[p], ld, n_f, c, vec);
-    p = min(4 + g, last);
-    int j1 = ix[p];
-    float r1 = vx[p];
-    int s = 0;
-    for (; s + 1 < ng; s += 2) {
-        gather_row<T, NB>(buf1, Y, j1, ld, n_f, c, vec);
-        p = min(4 * (s + 2) + g, last);
-        const int j0 = ix[p];
-        const float rn0 = vx[p];
-        finish_operand<T, NB>(buf0, 4 * s + g <= last, (T)r0, n_f, c);
-        gram_update<T, NB>(A, buf0);
-        gather_row<T, NB>(buf0, Y, j0, ld, n_f, c, vec);
-        p = min(4 * (s + 3) + g, last);
-        j1 = ix[p];
-        const float rn1 = vx[p];
-        finish_operand<T, NB>(buf1, 4 * (s + 1) + g <= last, (T)r1, n_f, c);
-        gram_update<T, NB>(A, buf1);
-        r0 = rn0;
-        r1 = rn1;
+    T buf[D][NB];
+    float rv[D];      // rating of the group in buf[k]
+    int jq[D];        // id ring: group X's id in jq[X % D] until its gather is issued
+    float rq[D];
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k) {  // groups 0 .. D - 2: gathered now
+        const int p = min(4 * k + g, last);
+        rv[k] = vx[p];
+        gather_row<T, NB, VEC>(buf[k], Y, ix[p], ld, n_f, c);
     }
-    if (s < ng) {
-        finish_operand<T, NB>(buf0, 4 * s + g <= last, (T)r0, n_f, c);
-        gram_update<T, NB>(A, buf0);
+#pragma unroll
+    for (int x = D - 1; x < 2 * D - 1; ++x) {  // ids of groups D - 1 .. 2 D - 2
+        const int p = min(4 * x + g, last);
+        jq[x % D] = ix[p];
+        rq[x % D] = vx[p];
+    }
+    for (int s = 0; s < ng; s += D) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            // group s + k is in buf[k]; gather group s + k + D - 1, then load
+            // the id of group s + k + 2 D - 1 into the slot that freed
+            const int slot = (k + D - 1) % D;
+            gather_row<T, NB, VEC>(buf[slot], Y, jq[slot], ld, n_f, c);
+            rv[slot] = rq[slot];
+            const int p = min(4 * (s + k + 2 * D - 1) + g, last);
+            jq[slot] = ix[p];
+            rq[slot] = vx[p];
+            if (s + k < ng) {
+                finish_operand<T, NB>(buf[k], 4 * (s + k) + g <= last, (T)rv[k], n_f, c);
+                gram_update<T, NB>(A, buf[k]);
+            }
+        }
     }
 }
 
@@ -287,7 +304,7 @@ template <typename T, int NB> struct Occ {
 
 // One chunk: Gram of its ratings, then either the partial tiles (split row)
 // or the row solve.
-template <typename T, int NB>
+template <typename T, int NB, bool VEC>
 __device__ __forceinline__ void sweep_chunk(
     int64_t q, const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
@@ -295,7 +312,7 @@ __device__ __forceinline__ void sweep_chunk(
     const int32_t *__restrict__ chunk_len, const int32_t *__restrict__ chunk_slot,
     typename Mfma<T>::acc4 *__restrict__ partial, const T *__restrict__ X_at,
     T *__restrict__ grad_out, int64_t *__restrict__ bad_row, int32_t *__restrict__ status,
-    int empty_status, int vec, T *sm) {
+    int empty_status, T *sm) {
     typedef typename Mfma<T>::acc4 acc4;
     typedef Tri<NB> TR;
     const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
@@ -315,7 +332,7 @@ __device__ __forceinline__ void sweep_chunk(
     acc4 A[TR::NT];
 #pragma unroll
     for (int t = 0; t < TR::NT; ++t) A[t] = acc4{T(0), T(0), T(0), T(0)};
-    gram_accumulate<T, NB>(A, idx, val, b, b + len, Y, ld, n_f, g, c, vec != 0);
+    gram_accumulate<T, NB, VEC>(A, idx, val, b, b + len, Y, ld, n_f, g, c);
     if (slot >= 0) {
         acc4 *dst = partial + (int64_t)slot * TR::NT * kWave;
 #pragma unroll
@@ -331,7 +348,7 @@ __device__ __forceinline__ void sweep_chunk(
 // striding over the chunks (PERSIST = true; chunks are ordered longest
 // first, so the stride deals them out like a greedy schedule).
 // chunk_row == nullptr: chunk q is row q in full (fold-in and unplanned use).
-template <typename T, int NB, bool PERSIST>
+template <typename T, int NB, bool PERSIST, bool VEC>
 __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
@@ -339,19 +356,19 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ chunk_slot, typename Mfma<T>::acc4 *__restrict__ partial,
     const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row,
-    int32_t *__restrict__ status, int empty_status, int vec) {
+    int32_t *__restrict__ status, int empty_status) {
     __shared__ T sm[Shared<T, NB>::size];
     if constexpr (PERSIST) {
         for (int64_t q = blockIdx.x; q < n_chunks; q += gridDim.x)
-            sweep_chunk<T, NB>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row, chunk_begin,
-                               chunk_len, chunk_slot, partial, X_at, grad_out, bad_row, status,
-                               empty_status, vec, sm);
+            sweep_chunk<T, NB, VEC>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row,
+                                    chunk_begin, chunk_len, chunk_slot, partial, X_at, grad_out,
+                                    bad_row, status, empty_status, sm);
     } else {
         const int64_t q = blockIdx.x;
         if (q >= n_chunks) return;
-        sweep_chunk<T, NB>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row, chunk_begin,
-                           chunk_len, chunk_slot, partial, X_at, grad_out, bad_row, status,
-                           empty_status, vec, sm);
+        sweep_chunk<T, NB, VEC>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row,
+                                chunk_begin, chunk_len, chunk_slot, partial, X_at, grad_out,
+                                bad_row, status, empty_status, sm);
     }
 }
 
@@ -387,20 +404,19 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_split_kernel(
 
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 
-template <typename T, int NB>
-int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
+template <typename T, int NB, bool VEC>
+int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
               T lambda, const T *X_at, T *grad_out, int64_t *bad_row, int32_t *status, int empty_status,
               int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
     typedef typename Mfma<T>::acc4 acc4;
     typedef Tri<NB> TR;
-    const int vec = sizeof(T) == 4 && ld % 4 == 0 && ((uintptr_t)Y % 16) == 0;
     if (bad_row) hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, bad_row, (int64_t)LLONG_MAX);
     if (!plan) {
         if (n_rows_unplanned > 0)
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false>), dim3((unsigned)n_rows_unplanned),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)n_rows_unplanned),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
                                lambda, n_rows_unplanned, nullptr, nullptr, nullptr, nullptr,
-                               (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status, vec);
+                               (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status);
         return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
     }
     acc4 *partial = (acc4 *)partial_ext;
@@ -411,18 +427,18 @@ int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, in
     }
     if (plan->n_chunks > 0) {
         if (plan->grid > 0)
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true>),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true, VEC>),
                                dim3((unsigned)std::min<int64_t>(plan->grid, plan->n_chunks)),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
                                lambda, plan->n_chunks, plan->chunk_row, plan->chunk_begin,
                                plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
-                               status, empty_status, vec);
+                               status, empty_status);
         else
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false>), dim3((unsigned)plan->n_chunks),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)plan->n_chunks),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
                                lambda, plan->n_chunks, plan->chunk_row, plan->chunk_begin,
                                plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
-                               status, empty_status, vec);
+                               status, empty_status);
     }
     if (plan->n_split_rows > 0)
         hipLaunchKernelGGL((sweep_split_kernel<T, NB>), dim3((unsigned)plan->n_split_rows),
@@ -430,6 +446,20 @@ int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, in
                            plan->split_row, plan->split_slot0, plan->split_nslot, partial, X_at,
                            grad_out, bad_row, status);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
+template <typename T, int NB>
+int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
+              T lambda, const T *X_at, T *grad_out, int64_t *bad_row, int32_t *status, int empty_status,
+              int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (ld % 4 == 0 && ((uintptr_t)Y % 16) == 0)
+            return run_sweep_v<T, NB, true>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out,
+                                            bad_row, status, empty_status, n_rows_unplanned,
+                                            partial_ext, s);
+    }
+    return run_sweep_v<T, NB, false>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out, bad_row,
+                                     status, empty_status, n_rows_unplanned, partial_ext, s);
 }
 
 template <typename T>
