@@ -116,6 +116,11 @@ __device__ __forceinline__ void load_own(typename Vec<T, VEC>::type (&v)[NV], co
 }
 
 // Minimum wavefronts per SIMD asked of the compiler for the chunk kernels:
+// Gathered groups of ratings in flight per wavefront (register buffers) in
+// the gradient and coefficient loops.
+constexpr int kGradDepth = 2;
+constexpr int kCoefDepth = 2;
+
 // 4 for the FP32 vector-of-4 instances with one workgroup per chunk (at most
 // 128 VGPRs, which they fit without spilling), no constraint for the others.
 template <typename T, int VEC, bool PERSIST>
@@ -179,13 +184,16 @@ __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void grad_chunks
     for (int k = 0; k < NV; ++k) acc[k] = vzero<T, VEC>();
     double e2 = 0.0;
     if (b < e) {
-        // rating t + g of a group: id (a row of this chunk past the end), value
-        const int jl = idx[e - 1];
-        auto rid = [&](int64_t t, bool &ok, T &r) -> int {
-            ok = t < e;
-            r = ok ? (T)val[t] : T(0);
-            return ok ? idx[t] : jl;
-        };
+        // Group X holds ratings b + X GR + g.  D buffers of gathered rows
+        // rotate; a group's ids are loaded D steps before its gather (ring
+        // jq), since the wait counter completes loads in issue order and a
+        // later id load would make each wait drain the gathers in flight; its
+        // values are loaded with the gather (no register copy of a load in
+        // flight, which would wait for it).  Lanes past the end use the
+        // chunk's last rating (a valid row) and contribute nothing.
+        constexpr int D = kGradDepth;
+        const int64_t ngr = (e - b + GR - 1) / GR;
+        auto pos = [&](int64_t x) -> int64_t { return min(b + x * GR + g, e - 1); };
         auto step = [&](const V (&y)[NV], bool ok, T r) {
             T d = T(0);
 #pragma unroll
@@ -196,27 +204,25 @@ __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void grad_chunks
             for (int k = 0; k < NV; ++k) acc[k] += res * y[k];
             if (c == 0) e2 += (double)res * (double)res;
         };
-        // two buffers: group t in A, group t + GR in B (ids one group ahead)
-        V ya[NV], yb[NV];
-        bool oka, okb;
-        T ra, rb;
-        gather_row<T, VEC, NV, L>(ya, Y, rid(b + g, oka, ra), ld, c, cl);
-        int jb = rid(b + GR + g, okb, rb);
-        for (int64_t t = b; t < e; t += 2 * GR) {
-            gather_row<T, VEC, NV, L>(yb, Y, jb, ld, c, cl);
-            bool okn;
-            T rn;
-            const int jn = rid(t + 2 * GR + g, okn, rn);
-            step(ya, oka, ra);
-            gather_row<T, VEC, NV, L>(ya, Y, jn, ld, c, cl);
-            bool okm;
-            T rm;
-            jb = rid(t + 3 * GR + g, okm, rm);
-            step(yb, okb, rb);
-            oka = okn;
-            ra = rn;
-            okb = okm;
-            rb = rm;
+        V ys[D][NV];
+        T rv[D];
+        int jq[D];
+#pragma unroll
+        for (int k = 0; k < D - 1; ++k) {
+            gather_row<T, VEC, NV, L>(ys[k], Y, idx[pos(k)], ld, c, cl);
+            rv[k] = (T)val[pos(k)];
+        }
+#pragma unroll
+        for (int k = D - 1; k < 2 * D - 1; ++k) jq[k % D] = idx[pos(k)];
+        for (int64_t s0 = 0; s0 < ngr; s0 += D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int slot = (k + D - 1) % D;
+                gather_row<T, VEC, NV, L>(ys[slot], Y, jq[slot], ld, c, cl);
+                rv[slot] = (T)val[pos(s0 + k + D - 1)];
+                jq[slot] = idx[pos(s0 + k + 2 * D - 1)];
+                if (s0 + k < ngr) step(ys[k], b + (s0 + k) * GR + g < e, rv[k]);
+            }
         }
     }
     if (!cl.last_ok) acc[NV - 1] = vzero<T, VEC>();  // duplicated columns
@@ -318,13 +324,11 @@ __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void coeff_chunk
     load_own<T, VEC, NV, L>(pu, PU, row, ld, c, cl);
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
     if (b < e) {
-        // rating t + g of a group: id (a row of this chunk past the end), value
-        const int jl = idx[e - 1];
-        auto rid = [&](int64_t t, bool &ok, float &r) -> int {
-            ok = t < e;
-            r = ok ? val[t] : 0.0f;
-            return ok ? idx[t] : jl;
-        };
+        // Same pipeline as grad_chunks_kernel: D buffers of gathered item rows
+        // (x and p), ids D steps ahead of their gathers, values with them.
+        constexpr int D = kCoefDepth;
+        const int64_t ngr = (e - b + GR - 1) / GR;
+        auto pos = [&](int64_t x) -> int64_t { return min(b + x * GR + g, e - 1); };
         auto step = [&](const V (&xm)[NV], const V (&pm)[NV], bool ok, float r) {
             // one FMA chain per dot product (a1 takes both of its terms)
             T a0 = T(0), a1 = T(0), a2 = T(0);
@@ -351,33 +355,28 @@ __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void coeff_chunk
                 c4 += A2 * A2;
             }
         };
-        // two buffers: group t in A, group t + GR in B (ids one group ahead)
-        V xa[NV], pa[NV], xb[NV], pb[NV];
-        bool oka, okb;
-        float ra, rb;
-        {
-            const int j0 = rid(b + g, oka, ra);
-            gather_row<T, VEC, NV, L>(xa, XM, j0, ld, c, cl);
-            gather_row<T, VEC, NV, L>(pa, PM, j0, ld, c, cl);
+        V xs[D][NV], ps[D][NV];
+        float rv[D];
+        int jq[D];
+#pragma unroll
+        for (int k = 0; k < D - 1; ++k) {
+            const int j = idx[pos(k)];
+            gather_row<T, VEC, NV, L>(xs[k], XM, j, ld, c, cl);
+            gather_row<T, VEC, NV, L>(ps[k], PM, j, ld, c, cl);
+            rv[k] = val[pos(k)];
         }
-        int jb = rid(b + GR + g, okb, rb);
-        for (int64_t t = b; t < e; t += 2 * GR) {
-            gather_row<T, VEC, NV, L>(xb, XM, jb, ld, c, cl);
-            gather_row<T, VEC, NV, L>(pb, PM, jb, ld, c, cl);
-            bool okn;
-            float rn;
-            const int jn = rid(t + 2 * GR + g, okn, rn);
-            step(xa, pa, oka, ra);
-            gather_row<T, VEC, NV, L>(xa, XM, jn, ld, c, cl);
-            gather_row<T, VEC, NV, L>(pa, PM, jn, ld, c, cl);
-            bool okm;
-            float rm;
-            jb = rid(t + 3 * GR + g, okm, rm);
-            step(xb, pb, okb, rb);
-            oka = okn;
-            ra = rn;
-            okb = okm;
-            rb = rm;
+#pragma unroll
+        for (int k = D - 1; k < 2 * D - 1; ++k) jq[k % D] = idx[pos(k)];
+        for (int64_t s0 = 0; s0 < ngr; s0 += D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int slot = (k + D - 1) % D;
+                gather_row<T, VEC, NV, L>(xs[slot], XM, jq[slot], ld, c, cl);
+                gather_row<T, VEC, NV, L>(ps[slot], PM, jq[slot], ld, c, cl);
+                rv[slot] = val[pos(s0 + k + D - 1)];
+                jq[slot] = idx[pos(s0 + k + 2 * D - 1)];
+                if (s0 + k < ngr) step(xs[k], ps[k], b + (s0 + k) * GR + g < e, rv[k]);
+            }
         }
     }
     c0 = sum64(c0);
