@@ -146,7 +146,7 @@ __device__ __forceinline__ void gram_update(typename Mfma<T>::acc4 (&A)[Tri<NB>:
 // and has a single exit (exits in the middle make the allocator duplicate
 // the accumulators); groups past the end are skipped by a uniform branch.
 // Loads for groups past the end read valid addresses and are discarded.
-constexpr int kGramDepth = 4;
+constexpr int kGramDepth = 3;
 
 template <typename T, int NB, bool VEC>
 __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
