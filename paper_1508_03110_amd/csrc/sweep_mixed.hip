@@ -82,12 +82,15 @@ template <int NB> struct Raw {
     unsigned s[Slots16<NB>::NS];
 };
 
-template <int NB>
+// VEC (16-byte aligned rows of a multiple of 8 elements) is a template
+// parameter: a run-time choice would put a branch around every load, across
+// which the compiler waits for all loads in flight.
+template <int NB, bool VEC>
 __device__ __forceinline__ void gather16(Raw<NB> &w, const u16 *__restrict__ Y, int j, int ld,
-                                         int n_f, int c, bool vec) {
+                                         int n_f, int c) {
     typedef Slots16<NB> SL;
     const u16 *row = Y + (int64_t)j * ld;
-    if (vec) {
+    if constexpr (VEC) {
 #pragma unroll
         for (int q = 0; q < SL::O; ++q) {
             const u32x4 v = *(const u32x4 *)(row + 128 * q + 8 * c);
@@ -115,29 +118,12 @@ __device__ __forceinline__ void gather16(Raw<NB> &w, const u16 *__restrict__ Y, 
     }
 }
 
-// Ratings of one group for one lane group: ids and values of ratings
-// 32 s + 8 g + k (clamped to the last rating; masked at use).
-struct Ids {
-    int j[8];
-    float r[8];
-};
-
-__device__ __forceinline__ void load_ids(Ids &d, const int32_t *__restrict__ ix,
-                                         const float *__restrict__ vx, int s, int g, int last) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int p = min(32 * s + 8 * g + k, last);
-        d.j[k] = ix[p];
-        d.r[k] = vx[p];
-    }
-}
-
 // Operands of one group (8 ratings x NB blocks) from the loaded data, with the
 // masks: ratings past the end -> 0, slot n_f -> bf16(r), padding slots -> 0.
 // Then one MFMA per upper-triangular tile.
 template <int NB>
 __device__ __forceinline__ void gram_group(acc4 (&A)[Tri<NB>::NT], const Raw<NB> (&w)[8],
-                                           const float (&r)[8], int s, int g, int c, int last,
+                                           const unsigned (&rb)[8], int s, int g, int c, int last,
                                            int n_f) {
     typedef Slots16<NB> SL;
     unsigned mask[4];
@@ -165,7 +151,7 @@ __device__ __forceinline__ void gram_group(acc4 (&A)[Tri<NB>::NT], const Raw<NB>
         for (int m = 0; m < 4; ++m) {
             unsigned v = (w[2 * m].s[k] & 0xffffu) | (w[2 * m + 1].s[k] << 16);
             if (a == NB - 1) {
-                const unsigned rv = bf16_bits(r[2 * m]) | (bf16_bits(r[2 * m + 1]) << 16);
+                const unsigned rv = rb[2 * m] | (rb[2 * m + 1] << 16);
                 v = col < n_f ? v : (col == n_f ? rv : 0u);
             }
             op[a][m] = v & mask[m];
@@ -177,40 +163,65 @@ __device__ __forceinline__ void gram_group(acc4 (&A)[Tri<NB>::NT], const Raw<NB>
         for (int bb = a; bb < NB; ++bb) A[Tri<NB>::id(a, bb)] = mma_bf16(op[a], op[bb], A[Tri<NB>::id(a, bb)]);
 }
 
-// Gram accumulation over ratings [b, e), two register buffers alternating
-// (rows of group s + 1 and ids of group s + 2 in flight while group s is
-// consumed), single exit; loads past the end read valid clamped addresses.
-template <int NB>
+// Gram accumulation over ratings [b, e): group s holds ratings 32 s + 8 g +
+// k (clamped to the last rating; masked at use).  Two register buffers
+// alternate (the rows of group s + 1 in flight while group s is consumed);
+// the ids and values of a group are loaded two steps before its gather
+// (rings jq, rq) and the values turned into BF16 bits when the gather is
+// issued, so that no wait for an id or a value drains the gathers in flight
+// (the wait counter completes loads in issue order).  Single exit; loads
+// past the end read valid clamped addresses.
+template <int NB, bool VEC>
 __device__ __forceinline__ void gram_accumulate16(acc4 (&A)[Tri<NB>::NT],
                                                   const int32_t *__restrict__ idx,
                                                   const float *__restrict__ val, int64_t b,
                                                   int64_t e, const u16 *__restrict__ Y, int ld,
-                                                  int n_f, int g, int c, bool vec) {
+                                                  int n_f, int g, int c) {
     if (b >= e) return;
     const int last = (int)(e - 1 - b);
     const int ng = (last >> 5) + 1;
     const int32_t *ix = idx + b;
     const float *vx = val + b;
-    Raw<NB> w0[8], w1[8];
-    Ids i0, i1, in;
-    load_ids(i0, ix, vx, 0, g, last);
+    auto pos = [&](int s, int k) { return min(32 * s + 8 * g + k, last); };
+    Raw<NB> w[2][8];
+    unsigned rb[2][8];
+    int jq[2][8];
+    float rq[2][8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) gather16<NB>(w0[k], Y, i0.j[k], ld, n_f, c, vec);
-    load_ids(i1, ix, vx, 1, g, last);
-    int s = 0;
-    for (; s + 1 < ng; s += 2) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) gather16<NB>(w1[k], Y, i1.j[k], ld, n_f, c, vec);
-        load_ids(in, ix, vx, s + 2, g, last);
-        gram_group<NB>(A, w0, i0.r, s, g, c, last, n_f);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) gather16<NB>(w0[k], Y, in.j[k], ld, n_f, c, vec);
-        i0 = in;
-        load_ids(in, ix, vx, s + 3, g, last);
-        gram_group<NB>(A, w1, i1.r, s + 1, g, c, last, n_f);
-        i1 = in;
+    for (int k = 0; k < 8; ++k) {
+        gather16<NB, VEC>(w[0][k], Y, ix[pos(0, k)], ld, n_f, c);
+        rb[0][k] = bf16_bits(vx[pos(0, k)]);
     }
-    if (s < ng) gram_group<NB>(A, w0, i0.r, s, g, c, last, n_f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        jq[1][k] = ix[pos(1, k)];
+        rq[1][k] = vx[pos(1, k)];
+        jq[0][k] = ix[pos(2, k)];
+        rq[0][k] = vx[pos(2, k)];
+    }
+    for (int s = 0; s < ng; s += 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // group s + h is in w[h]; gather group s + h + 1, then load the
+            // ids of group s + h + 3 into the slot that freed
+            const int slot = 1 - h;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                gather16<NB, VEC>(w[slot][k], Y, jq[slot][k], ld, n_f, c);
+                rb[slot][k] = bf16_bits(rq[slot][k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                jq[slot][k] = ix[pos(s + h + 3, k)];
+                rq[slot][k] = vx[pos(s + h + 3, k)];
+            }
+            // keep the loads above the MFMAs of group s + h (the scheduler
+            // would sink them below and serialise the pipeline); not for the
+            // widest rows, whose tiles leave no registers for two buffers
+            if constexpr (NB <= 7) __builtin_amdgcn_sched_barrier(0);
+            if (s + h < ng) gram_group<NB>(A, w[h], rb[h], s + h, g, c, last, n_f);
+        }
+    }
 }
 
 // LDS of the mixed finish (floats).
@@ -223,41 +234,48 @@ template <int NB> struct SharedMx {
     static constexpr int size = 5 * NP + TS + NB * TS + 2 * NPV + 16;
 };
 
-// Partial residual sum_j (r_ij - y_j . x0) y_j over ratings [b, e) with FP32
-// factors; x0 (natural column order) in xn.  Lane (g, c) takes columns
-// 64 v + 4 c .. + 3 of ratings b + g + 4 k; ratings go in blocks of RU per
-// lane group, the rows of block s + 1 and the ids of block s + 2 in flight
-// while block s is consumed.  Returns the lane's column sums reduced over the
-// 4 lane groups (valid in every group).
-template <int NB> struct ResU {
-    static constexpr int U = NB <= 5 ? 4 : NB <= 7 ? 1 : 2;
-};
-
-template <int NV>
+// One FP32 factor row for the residual: lane c takes columns 64 v + 4 c ..
+// + 3.  Loads are unconditional: columns past n_f are clamped into the row
+// (their x0 is zero, so they add nothing to the dot product, and
+// write_residual drops their sums).  VEC: 16-byte loads (rows of a multiple
+// of 4 floats, 16-byte aligned, n_f a multiple of 4 so a vector never
+// straddles n_f).
+template <int NV, bool VEC>
 __device__ __forceinline__ void load_res_row(float (&y)[NV][4], const float *__restrict__ Y32,
-                                             int j, int ld, int n_f, int c, bool vec) {
+                                             int j, int ld, int n_f, int c) {
     const float *row = Y32 + (int64_t)j * ld;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int col = 64 * v + 4 * c;
-        if (vec) {
-            f4 q4 = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (col < n_f) q4 = *(const f4 *)(row + col);
+        if constexpr (VEC) {
+            const f4 q4 = *(const f4 *)(row + min(col, n_f - 4));
 #pragma unroll
             for (int q = 0; q < 4; ++q) y[v][q] = q4[q];
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) y[v][q] = col + q < n_f ? row[col + q] : 0.0f;
+            for (int q = 0; q < 4; ++q) y[v][q] = row[min(col + q, n_f - 1)];
         }
     }
 }
 
-template <int NB>
+// Partial residual sum_j (r_ij - y_j . x0) y_j over ratings [b, e) with FP32
+// factors; x0 (natural column order) in xn.  Lane (g, c) takes columns
+// 64 v + 4 c .. + 3 of ratings b + g + 4 k; ratings go in blocks of RU per
+// lane group.  Two register buffers alternate (the rows of block s + 1 in
+// flight while block s is consumed); ids and values are loaded two steps
+// before their gather (rings jq, rq), so that no wait drains the gathers in
+// flight.  Returns the lane's column sums reduced over the 4 lane groups
+// (valid in every group).
+template <int NB> struct ResU {
+    static constexpr int U = NB <= 5 ? 4 : NB <= 7 ? 1 : 2;
+};
+
+template <int NB, bool VEC>
 __device__ __forceinline__ void residual_stream(float (&res)[SharedMx<NB>::NV][4],
                                                 const int32_t *__restrict__ idx,
                                                 const float *__restrict__ val, int64_t b,
                                                 int64_t e, const float *__restrict__ Y32, int ld,
-                                                int n_f, const float *xn, int g, int c, bool vec) {
+                                                int n_f, const float *xn, int g, int c) {
     constexpr int NV = SharedMx<NB>::NV;
     constexpr int U = ResU<NB>::U;
     float xv[NV][4];
@@ -269,60 +287,54 @@ __device__ __forceinline__ void residual_stream(float (&res)[SharedMx<NB>::NV][4
             xv[v][q] = col < n_f ? xn[col] : 0.0f;  // zero past n_f masks padding columns
             res[v][q] = 0.0f;
         }
-    if (b >= e) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) res[v][q] = 0.0f;
-        return;
-    }
+    if (b >= e) return;
     const int64_t last = e - 1;
     // rating of lane group g, block s, slot u: b + g + 4 (U s + u), clamped
     auto at = [&](int64_t s, int u) { return min(b + g + 4 * (U * s + u), last); };
     auto okr = [&](int64_t s, int u) { return b + g + 4 * (U * s + u) <= last; };
     const int64_t nblk = (e - b + 4 * U - 1) / (4 * U);
-    float y0[U][NV][4], y1[U][NV][4];
-    float r0[U], r1[U], r2[U];
-    int j1[U], j2[U];
+    float y[2][U][NV][4];
+    float rv[2][U], rq[2][U];
+    int jq[2][U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int64_t p = at(0, u);
-        r0[u] = val[p];
-        load_res_row<NV>(y0[u], Y32, idx[p], ld, n_f, c, vec);
-        const int64_t p1 = at(1, u);
-        j1[u] = idx[p1];
-        r1[u] = val[p1];
+        load_res_row<NV, VEC>(y[0][u], Y32, idx[at(0, u)], ld, n_f, c);
+        rv[0][u] = val[at(0, u)];
+        jq[1][u] = idx[at(1, u)];
+        rq[1][u] = val[at(1, u)];
+        jq[0][u] = idx[at(2, u)];
+        rq[0][u] = val[at(2, u)];
     }
-    for (int64_t s = 0; s < nblk; ++s) {
+    for (int64_t s0 = 0; s0 < nblk; s0 += 2) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            load_res_row<NV>(y1[u], Y32, j1[u], ld, n_f, c, vec);
-            const int64_t p2 = at(s + 2, u);
-            j2[u] = idx[p2];
-            r2[u] = val[p2];
-        }
+        for (int h = 0; h < 2; ++h) {
+            const int slot = 1 - h;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            float dot = 0.0f;
+            for (int u = 0; u < U; ++u) {
+                load_res_row<NV, VEC>(y[slot][u], Y32, jq[slot][u], ld, n_f, c);
+                rv[slot][u] = rq[slot][u];
+            }
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+            for (int u = 0; u < U; ++u) {
+                jq[slot][u] = idx[at(s0 + h + 3, u)];
+                rq[slot][u] = val[at(s0 + h + 3, u)];
+            }
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads above the block's FMAs
+            if (s0 + h < nblk) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) dot += y0[u][v][q] * xv[v][q];
-            const float err = okr(s, u) ? r0[u] - sum16(dot) : 0.0f;
+                for (int u = 0; u < U; ++u) {
+                    float dot = 0.0f;
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+                    for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) res[v][q] += err * y0[u][v][q];
-        }
+                        for (int q = 0; q < 4; ++q) dot += y[h][u][v][q] * xv[v][q];
+                    const float err = okr(s0 + h, u) ? rv[h][u] - sum16(dot) : 0.0f;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+                    for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) y0[u][v][q] = y1[u][v][q];
-            r0[u] = r1[u];
-            r1[u] = r2[u];
-            j1[u] = j2[u];
+                        for (int q = 0; q < 4; ++q) res[v][q] += err * y[h][u][v][q];
+                }
+            }
         }
     }
 #pragma unroll
@@ -406,7 +418,10 @@ __device__ __forceinline__ void write_residual(const float (&res)[SharedMx<NB>::
 #pragma unroll
         for (int v = 0; v < SharedMx<NB>::NV; ++v)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dst[64 * v + 4 * c + q] = res[v][q];
+            for (int q = 0; q < 4; ++q) {
+                const int col = 64 * v + 4 * c + q;
+                dst[col] = col < n_f ? res[v][q] : 0.0f;  // clamped columns carry no data
+            }
     }
 }
 
@@ -428,7 +443,7 @@ struct MixArgs {
     int64_t *bad_row;
 };
 
-template <int NB>
+template <int NB, bool VEC16>
 __global__ __launch_bounds__(64, (OccMx<NB>::waves)) void sweep_mixed_chunks_kernel(
     MixArgs a, int64_t n_chunks, const int32_t *__restrict__ chunk_row,
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
@@ -446,7 +461,7 @@ __global__ __launch_bounds__(64, (OccMx<NB>::waves)) void sweep_mixed_chunks_ker
     acc4 A[TR::NT];
 #pragma unroll
     for (int t = 0; t < TR::NT; ++t) A[t] = acc4{0.0f, 0.0f, 0.0f, 0.0f};
-    gram_accumulate16<NB>(A, a.idx, a.val, b, b + len, a.Y16, a.ld, a.n_f, g, c, a.vec16 != 0);
+    gram_accumulate16<NB, VEC16>(A, a.idx, a.val, b, b + len, a.Y16, a.ld, a.n_f, g, c);
     if (slot >= 0) {
         acc4 *dst = partial + (int64_t)slot * TR::NT * kWave;
 #pragma unroll
@@ -470,7 +485,10 @@ __global__ __launch_bounds__(64, (OccMx<NB>::waves)) void sweep_mixed_chunks_ker
         float *wn = xn + SM::NPV;
         to_natural<NB>(xs, xn, n_f);
         float res[SM::NV][4];
-        residual_stream<NB>(res, a.idx, a.val, b, b + len, a.Y32, a.ld, n_f, xn, g, c, a.vec32 != 0);
+        if (a.vec32)
+            residual_stream<NB, true>(res, a.idx, a.val, b, b + len, a.Y32, a.ld, n_f, xn, g, c);
+        else
+            residual_stream<NB, false>(res, a.idx, a.val, b, b + len, a.Y32, a.ld, n_f, xn, g, c);
         write_residual<NB>(res, wn, n_f);
         __syncthreads();
         refine_solve<NB>(A, n_f, reg, xs, wn, sm);
@@ -554,7 +572,10 @@ __global__ __launch_bounds__(64) void mixed_residual_kernel(
     for (int i = lane; i < SM::NPV; i += kWave) xn[i] = i < a.n_f ? a.X32[row * (int64_t)a.ld + i] : 0.0f;
     __syncthreads();
     float res[SM::NV][4];
-    residual_stream<NB>(res, a.idx, a.val, b, e, a.Y32, a.ld, a.n_f, xn, g, c, a.vec32 != 0);
+    if (a.vec32)
+        residual_stream<NB, true>(res, a.idx, a.val, b, e, a.Y32, a.ld, a.n_f, xn, g, c);
+    else
+        residual_stream<NB, false>(res, a.idx, a.val, b, e, a.Y32, a.ld, a.n_f, xn, g, c);
     write_residual<NB>(res, rpart + w * (int64_t)SM::NPV, a.n_f);
 }
 
@@ -617,10 +638,16 @@ int run_mixed(Ctx *ctx, const Plan *plan, const als_csr *R, const MixArgs &a, hi
         fstore = (float *)(ws + p_bytes);
         rpart = (float *)(ws + p_bytes + f_bytes);
     }
-    if (plan->n_chunks > 0)
-        hipLaunchKernelGGL((sweep_mixed_chunks_kernel<NB>), dim3((unsigned)plan->n_chunks), dim3(kWave),
-                           0, s, a, plan->n_chunks, plan->chunk_row, plan->chunk_begin,
-                           plan->chunk_len, plan->chunk_slot, partial);
+    if (plan->n_chunks > 0) {
+        if (a.vec16)
+            hipLaunchKernelGGL((sweep_mixed_chunks_kernel<NB, true>), dim3((unsigned)plan->n_chunks),
+                               dim3(kWave), 0, s, a, plan->n_chunks, plan->chunk_row,
+                               plan->chunk_begin, plan->chunk_len, plan->chunk_slot, partial);
+        else
+            hipLaunchKernelGGL((sweep_mixed_chunks_kernel<NB, false>), dim3((unsigned)plan->n_chunks),
+                               dim3(kWave), 0, s, a, plan->n_chunks, plan->chunk_row,
+                               plan->chunk_begin, plan->chunk_len, plan->chunk_slot, partial);
+    }
     if (plan->n_split_rows > 0) {
         hipLaunchKernelGGL((sweep_mixed_split_kernel<NB>), dim3((unsigned)plan->n_split_rows),
                            dim3(kWave), 0, s, a, plan->n_split_rows, plan->split_row,
@@ -662,7 +689,7 @@ int launch_sweep_mixed(Ctx *ctx, const Plan *plan, const als_csr *R, const void 
     a.lambda = (float)lambda;
     a.refine = refine ? 1 : 0;
     a.vec16 = (ld % 8 == 0 && ((uintptr_t)Y16 % 16) == 0) ? 1 : 0;
-    a.vec32 = (!Y32 || (ld % 4 == 0 && ((uintptr_t)Y32 % 16) == 0)) ? 1 : 0;
+    a.vec32 = (!Y32 || (n_f % 4 == 0 && ld % 4 == 0 && ((uintptr_t)Y32 % 16) == 0)) ? 1 : 0;
     a.bad_row = bad_row;
     const int nb = (n_f + 1 + 15) / 16;
     switch (nb) {
