@@ -8,10 +8,9 @@
 // group of 64 / L and on factor columns c, c + L, ... of it (in vectors of
 // VEC), so every gathered factor row is read as L consecutive vectors.  Dot
 // products are formed in the factor type and reduced across the L lanes of a
-// rating; everything that
-// enters f, ||g||^2 or the quartic coefficients is accumulated in FP64 and
-// stored as one partial per chunk (or per block), then summed in a fixed
-// order, so results are bitwise reproducible.
+// rating; everything that enters f, ||g||^2 or the quartic coefficients is
+// accumulated in FP64 and stored as one partial per chunk (or per block),
+// then summed in a fixed order, so results are bitwise reproducible.
 #include <initializer_list>
 
 #include <algorithm>
@@ -160,8 +159,7 @@ template <int L, typename T> __device__ __forceinline__ T sum_group(T v) {
 //   G[i] = 2 lambda n_i X[i] + 2 sum_j Y[j] (X[i].Y[j] - r_ij).
 // scal[2q] receives this chunk's share of f, scal[2q + 1] of ||G||^2 (rows
 // that are whole in this chunk); split rows leave the regulariser and ||G||^2
-// to grad_split_kernel.  Rating ids are fetched two groups ahead and factor
-// rows one group ahead of their use.
+// to grad_split_kernel.
 template <typename T, int VEC, int NV, int L, bool PERSIST>
 __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void grad_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,

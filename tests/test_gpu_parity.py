@@ -184,13 +184,13 @@ def test_sweep_is_deterministic(ctx, c0):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("chunk", [0, 8])
-@pytest.mark.parametrize("n_f", [20, 50, 100, 140])
+@pytest.mark.parametrize("n_f", [20, 50, 65, 100, 128, 140])
 def test_gradient_and_loss(ctx, dtype, chunk, n_f):
     """Both gradient blocks and f; FP32 n_f = 20 and 100 take the 4-wide
     gather with 8 lanes per rating (the last vector of a lane clamped inside
-    the row), 140 the 4-wide gather with 16 lanes, n_f = 50 the one-element
-    gather with 8 lanes; FP64 n_f = 100 and 140 the one-element gather with
-    16 lanes."""
+    the row), 128 the same with every vector real, 140 the 4-wide gather with
+    16 lanes, n_f = 50 the one-element gather with 8 lanes and 65 with 16;
+    FP64 n_f = 65, 100, 128 and 140 the one-element gather with 16 lanes."""
     P = synth.random_problem(90, 70, n_f=n_f, lam=0.07, seed=21, density=0.15, long_rows=2,
                              empty_rows=3, x0_sigma=0.5)
     U0 = P.U0 if dtype == torch.float64 else r32(P.U0)
@@ -214,7 +214,7 @@ def test_gradient_and_loss(ctx, dtype, chunk, n_f):
 # ---------------------------------------------------------------- quartic coefficients
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("n_f", [3, 16, 100, 140])
+@pytest.mark.parametrize("n_f", [3, 16, 65, 100, 128, 140])
 def test_linesearch_coefficients(ctx, dtype, n_f):
     P = synth.random_problem(80, 60, n_f=n_f, lam=0.05, seed=30 + n_f, density=0.2,
                              long_rows=2, empty_rows=2, x0_sigma=0.3)
