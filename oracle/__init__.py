@@ -18,6 +18,9 @@ outer algorithms in numpy float64:
                         search (used to check the PCG equivalence the paper
                         states for convex quadratics).
 
+The submodule ``ranking`` holds the top-t ranking accuracy of Section IV (a
+modified Kendall tau distance between the top-t rankings of two solutions).
+
 Every function cites the passage it implements.  Parity is pinned by the CPU
 tests (brute-force least squares, block-gradient zero, monotone ALS, quartic
 against direct evaluation, finite differences, closed forms).
@@ -31,6 +34,8 @@ import subprocess
 from typing import Callable, Optional
 
 import numpy as np
+
+from . import ranking  # noqa: E402,F401  (Section IV ranking accuracy)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "als_oracle.c")
