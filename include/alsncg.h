@@ -317,6 +317,40 @@ ALS_API int ncg_direction_dev(als_ctx *ctx, int64_t n, const void *x, void *xbar
                               const void *g_new, const void *g_old, void *p, double *scal,
                               const double *restart_flag, int pr_plus, als_dtype dt, void *stream);
 
+/* ---------------------------------------------------------------- ranking accuracy
+ *
+ * Section IV measures how close a solution is to the converged one by the
+ * top-t rankings of every user: a modified Kendall tau distance counts the
+ * adjacent swaps that bring the converged solution's top t items, in order,
+ * to the front of the current ranking, normalised by its largest value.
+ *
+ * A user's ranking lists all items by decreasing predicted rating
+ * U[i] . M[j], formed in FP64 (FP32 factors are widened), equal ratings by
+ * increasing item id.  U: [n_u, ld], M: [n_m, ld] (device, element type dt =
+ * ALS_F32 or ALS_F64); 1 <= n_f <= 128, ld >= n_f; 1 <= t <= 32, t <= n_m.
+ * Factors must be finite.
+ */
+
+/* top (device int32 [n_u, t], row-major, caller-owned): the first t items of
+ * every user's ranking, best first.  n_u = 0 does nothing.  Errors:
+ * ALS_E_INVAL for a NULL pointer or a size outside the limits above. */
+ALS_API int rank_top_t(als_ctx *ctx, const void *U, const void *M, int64_t n_u, int64_t n_m,
+                       int n_f, int ld, als_dtype dt, int t, int32_t *top, void *stream);
+
+/* Ranking accuracy of (U, M) against reference lists top [n_u, t] (distinct
+ * item ids per row, e.g. rank_top_t of the converged factors): for user i,
+ * s_i = the number of adjacent swaps that move the reference items
+ * top[i][0], top[i][1], ... one after the other to places 1, 2, ... of the
+ * current ranking (Section IV), and q_i = 1 - s_i / s_max with
+ * s_max = t (2 n_m - t - 1) / 2.  swaps (device int64 [n_u], may be NULL)
+ * receives s_i; mean_q (device double [1], may be NULL) the mean of q_i,
+ * computed as 1 - (sum_i s_i) / (n_u s_max) from the exact integer sum.
+ * Needs n_u >= 1 and n_m >= 2; uses 8 bytes of context workspace.  Errors as
+ * rank_top_t. */
+ALS_API int rank_accuracy(als_ctx *ctx, const void *U, const void *M, int64_t n_u, int64_t n_m,
+                          int n_f, int ld, als_dtype dt, int t, const int32_t *top,
+                          int64_t *swaps, double *mean_q, void *stream);
+
 /* ---------------------------------------------------------------- serving
  *
  * Fold-in server: new users (requests) are solved against fixed item factors

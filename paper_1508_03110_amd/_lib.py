@@ -68,6 +68,8 @@ _SIGS = {
     "ncg_linesearch_exact": (_i, [_vp, _vp, _d, _vp, _vp, _vp]),
     "ncg_direction_dev": (_i, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
     "fold_in": (_i, [_vp, _vp, _i64, _i, _i, _d, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rank_top_t": (_i, [_vp, _vp, _vp, _i64, _i64, _i, _i, _i, _i, _vp, _vp]),
+    "rank_accuracy": (_i, [_vp, _vp, _vp, _i64, _i64, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
     "als_server_create": (_i, [_vp, _vp, _i64, _i, _i, _d, _i, ctypes.POINTER(ServerConfig),
                                ctypes.POINTER(_vp)]),
     "als_server_destroy": (None, [_vp]),
@@ -253,6 +255,20 @@ def fold_in(ctx, M, n_items, n_f, ld, lam, dt, n_req, req_indptr, req_items, req
                                             int(dt), int(n_req), _ptr(req_indptr), _ptr(req_items),
                                             _ptr(req_vals), _ptr(U_out), _ptr(req_status),
                                             _stream(stream)))
+
+
+# ---------------------------------------------------------------- ranking accuracy
+
+def rank_top_t(ctx, U, M, n_u, n_m, n_f, ld, dt, t, top, stream=None):
+    return _check("rank_top_t", load().rank_top_t(ctx, _ptr(U), _ptr(M), int(n_u), int(n_m), int(n_f),
+                                                  int(ld), int(dt), int(t), _ptr(top),
+                                                  _stream(stream)))
+
+
+def rank_accuracy(ctx, U, M, n_u, n_m, n_f, ld, dt, t, top, swaps=None, mean_q=None, stream=None):
+    return _check("rank_accuracy", load().rank_accuracy(ctx, _ptr(U), _ptr(M), int(n_u), int(n_m),
+                                                        int(n_f), int(ld), int(dt), int(t), _ptr(top),
+                                                        _ptr(swaps), _ptr(mean_q), _stream(stream)))
 
 
 # ---------------------------------------------------------------- fold-in server

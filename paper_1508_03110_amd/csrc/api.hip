@@ -397,6 +397,28 @@ int ncg_linesearch_step(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, 
     return rc;
 }
 
+static bool rank_args_ok(const void *U, const void *M, int64_t n_u, int64_t n_m, int n_f, int ld,
+                         als_dtype dt, int t) {
+    return U && M && n_u >= 0 && n_u <= INT32_MAX && n_m >= 1 && n_m <= INT32_MAX - 64 && n_f >= 1 &&
+           n_f <= 128 && ld >= n_f && (dt == ALS_F32 || dt == ALS_F64) && t >= 1 && t <= 32 &&
+           t <= n_m;
+}
+
+int rank_top_t(als_ctx *ctx, const void *U, const void *M, int64_t n_u, int64_t n_m, int n_f,
+               int ld, als_dtype dt, int t, int32_t *top, void *stream) {
+    if (!ctx || !top || !rank_args_ok(U, M, n_u, n_m, n_f, ld, dt, t)) return ALS_E_INVAL;
+    return launch_rank_top(U, M, n_u, (int)n_m, n_f, ld, dt, t, top, (hipStream_t)stream);
+}
+
+int rank_accuracy(als_ctx *ctx, const void *U, const void *M, int64_t n_u, int64_t n_m, int n_f,
+                  int ld, als_dtype dt, int t, const int32_t *top, int64_t *swaps, double *mean_q,
+                  void *stream) {
+    if (!ctx || !top || !rank_args_ok(U, M, n_u, n_m, n_f, ld, dt, t) || n_u < 1 || n_m < 2)
+        return ALS_E_INVAL;
+    return launch_rank_accuracy(ctx, U, M, n_u, (int)n_m, n_f, ld, dt, t, top, swaps, mean_q,
+                                (hipStream_t)stream);
+}
+
 int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int ld, double lambda,
             als_dtype dt, int64_t n_req, const int64_t *req_indptr, const int32_t *req_items,
             const float *req_vals, void *U_out, int32_t *req_status, void *stream) {

@@ -198,6 +198,13 @@ int launch_ls_final(double *state, int exact, double alpha0, double tau, double 
 int launch_quartic_min(const double *coeffs, double c, double *alpha_out, int32_t *trials_out,
                        hipStream_t s);
 
+// Top-t rankings and ranking accuracy (rank.hip).
+int launch_rank_top(const void *U, const void *M, int64_t n_u, int n_m, int n_f, int ld,
+                    als_dtype dt, int t, int32_t *top, hipStream_t s);
+int launch_rank_accuracy(Ctx *ctx, const void *U, const void *M, int64_t n_u, int n_m, int n_f,
+                         int ld, als_dtype dt, int t, const int32_t *top, int64_t *swaps,
+                         double *mean_q, hipStream_t s);
+
 // Deterministic FP64 column sums of a row-major [rows, cols] array, cols <= 8
 // (two launches, fixed order).  out[k] = sum_r parts[r * cols + k] (+ out[k]
 // when accumulate != 0).  stage: device scratch of kSumStageDoubles doubles.

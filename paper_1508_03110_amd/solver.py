@@ -458,6 +458,29 @@ def fold_in(ctx: Context, M, lam: float, req, n_f: int, ld: Optional[int] = None
     return U, st
 
 
+def rank_top_t(ctx: Context, U, M, t: int, n_f: Optional[int] = None):
+    """Top-t items of every user's ranking by U . M^T (Section IV), device
+    int32 [n_u, t].  U [n_u, ld], M [n_m, ld] device factors."""
+    n_f = int(n_f or U.shape[1])
+    top = torch.empty((U.shape[0], int(t)), dtype=torch.int32, device=ctx.torch_device)
+    L.rank_top_t(ctx.handle, U, M, U.shape[0], M.shape[0], n_f, U.shape[1], L.dtype_code(U.dtype),
+                 int(t), top)
+    return top
+
+
+def rank_accuracy(ctx: Context, U, M, top, n_f: Optional[int] = None, swaps: bool = False):
+    """Ranking accuracy of Section IV of (U, M) against reference top-t lists
+    `top` (device int32 [n_u, t]): device double [1] holding the mean of
+    q_i = 1 - s_i / s_max, and with swaps=True also the device int64 s_i."""
+    n_f = int(n_f or U.shape[1])
+    dev = ctx.torch_device
+    mean_q = torch.empty(1, dtype=torch.float64, device=dev)
+    s = torch.empty(U.shape[0], dtype=torch.int64, device=dev) if swaps else None
+    L.rank_accuracy(ctx.handle, U, M, U.shape[0], M.shape[0], n_f, U.shape[1], L.dtype_code(U.dtype),
+                    top.shape[1], top, s, mean_q)
+    return (mean_q, s) if swaps else mean_q
+
+
 class FoldInServer:
     """Continuous-batching fold-in server (als_server_*) against device item
     factors M [n_items, ld]; host numpy in, host numpy out."""
