@@ -99,16 +99,52 @@ def load_fstar():
         return None
 
 
+RANK_T = 20  # top-t of the ranking accuracy (Section IV uses t = 20)
+
+
+def ranking_kernels(DP, x, reps=3):
+    """Average time of rank_top_t and rank_accuracy (HIP events on torch's
+    current stream, where the binding launches them) at the problem's shape."""
+    import torch
+
+    from paper_1508_03110_amd.solver import rank_accuracy, rank_top_t
+    U, M = DP.U(x), DP.M(x)
+    top = rank_top_t(DP.ctx, U, M, RANK_T, n_f=DP.n_f)
+    rank_accuracy(DP.ctx, U, M, top, n_f=DP.n_f)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        rank_top_t(DP.ctx, U, M, RANK_T, n_f=DP.n_f)
+    ev[1].record()
+    for _ in range(reps):
+        q = rank_accuracy(DP.ctx, U, M, top, n_f=DP.n_f)
+    ev[2].record()
+    torch.cuda.synchronize()
+    flops = 2.0 * DP.n_u * DP.n_m * DP.n_f
+    t_top, t_acc = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+    return {"t": RANK_T, "users": DP.n_u, "items": DP.n_m, "top_t_ms": round(t_top, 3),
+            "accuracy_ms": round(t_acc, 3), "self_accuracy": q.item(),
+            "rating_tflops_fp64": {"top_t": round(flops / t_top / 1e9, 2),
+                                   "accuracy": round(flops / t_acc / 1e9, 2), "peak": 78.6}}
+
+
 def time_to_tol(DP, P, fstar, tol=1e-6, gtol=1e-6, max_als=2500, max_ncg=600):
     """Wall time for ALS (Algorithm 1) and ALS-NCG (Algorithm 2) from the same
     x0 to a relative f-gap (f - f*)/f* <= tol, and to the paper's stopping
     rule (1/N)||g|| <= gtol (Section IV).  As in the paper's timing method
     (Section VI), a traced run (f and ||g|| evaluated every iteration) finds the
-    iteration counts and a separate run without the diagnostics is timed."""
+    iteration counts and a separate run without the diagnostics is timed.
+
+    Also the time to a top-20 ranking accuracy of 70/80/90/100 % (Section IV,
+    Tables III and IV): the traced runs keep x on the device (every ALS-NCG
+    iteration; every ALS sweep up to 100, then every 10th), each algorithm's
+    final traced iterate gives the reference top-20 lists, and the first kept
+    iteration at each accuracy level is timed in the runs without
+    diagnostics."""
     import numpy as np
     import torch
 
-    from paper_1508_03110_amd.solver import Als, AlsNcg
+    from paper_1508_03110_amd.solver import Als, AlsNcg, rank_accuracy, rank_top_t
     U0 = P.U0.astype(np.float32)
     M0 = P.M0.astype(np.float32)
     N = P.n_f * (P.n_u + P.n_m)
@@ -122,29 +158,35 @@ def time_to_tol(DP, P, fstar, tol=1e-6, gtol=1e-6, max_als=2500, max_ncg=600):
     # ALS trace: f and ||g|| by one gradient pass per orientation after every sweep
     als = Als(DP, DP.pack(U0, M0))
     trace = []
+    keep_als = []
     for k in range(1, max_als + 1):
         als.sweep()
         f, g = DP.loss_and_gnorm(als.x)
         trace.append((k, f, g))
+        if k <= 100 or k % 10 == 0:
+            keep_als.append((k, als.x.clone()))
         kf, kg = crossing(trace)
         if kf is not None and kg is not None:
             break
     k_als = crossing(trace)
     # ALS-NCG traces (backtracking of Algorithm 4, and the exact minimiser of
     # the same quartic): f(x_k) = Q(alpha_k) and ||g_k|| come with every iteration
-    def ncg_trace(search):
+    def ncg_trace(search, keep=None):
         ncg = AlsNcg(DP, search=search).init(U0, M0)
         tr = []
         for k in range(1, max_ncg + 1):
             ncg.step()
             f = ncg.f if ncg.f == ncg.f else DP.loss_and_gnorm(ncg.x)[0]  # NaN after an ALS point
             tr.append((k, f, ncg.gnorm()))
+            if keep is not None:
+                keep.append((k, ncg.x.clone()))
             kf, kg = crossing(tr)
             if kf is not None and kg is not None:
                 break
         return tr
 
-    trace_n = ncg_trace("backtracking")
+    keep_ncg = []
+    trace_n = ncg_trace("backtracking", keep_ncg)
     k_ncg = crossing(trace_n)
     trace_e = ncg_trace("exact")
     k_exact = crossing(trace_e)
@@ -164,8 +206,24 @@ def time_to_tol(DP, P, fstar, tol=1e-6, gtol=1e-6, max_als=2500, max_ncg=600):
                 got[k] = time.perf_counter() - t
         return got
 
-    ta = timed(lambda: Als(DP, DP.pack(U0, M0)), lambda s: s.sweep(), k_als)
-    tn = timed(lambda: AlsNcg(DP).init(U0, M0), lambda s: s.step(), k_ncg)
+    # ranking accuracy of the kept iterates against each run's final one
+    levels = (0.70, 0.80, 0.90, 0.99, 0.999, 0.9999, 1.00)
+
+    def rank_levels(keep):
+        x_ref = keep[-1][1]
+        top = rank_top_t(DP.ctx, DP.U(x_ref), DP.M(x_ref), RANK_T, n_f=DP.n_f)
+        qs = [(k, rank_accuracy(DP.ctx, DP.U(x), DP.M(x), top, n_f=DP.n_f)) for k, x in keep]
+        torch.cuda.synchronize()
+        qs = [(k, float(q.item())) for k, q in qs]
+        keep.clear()
+        return qs, {lv: next((k for k, q in qs if q >= lv), None) for lv in levels}
+
+    q_als, r_als = rank_levels(keep_als)
+    q_ncg, r_ncg = rank_levels(keep_ncg)
+    ta = timed(lambda: Als(DP, DP.pack(U0, M0)), lambda s: s.sweep(),
+               list(k_als) + list(r_als.values()))
+    tn = timed(lambda: AlsNcg(DP).init(U0, M0), lambda s: s.step(),
+               list(k_ncg) + list(r_ncg.values()))
     te = timed(lambda: AlsNcg(DP, search="exact").init(U0, M0), lambda s: s.step(), k_exact)
     for name, ks, ts, tr in (("als", k_als, ta, trace), ("als_ncg", k_ncg, tn, trace_n),
                              ("als_ncg_exact_search", k_exact, te, trace_e)):
@@ -173,6 +231,19 @@ def time_to_tol(DP, P, fstar, tol=1e-6, gtol=1e-6, max_als=2500, max_ncg=600):
                      "iterations_to_g_tol": ks[1], "seconds_to_g_tol": ts.get(ks[1]),
                      "final_f": tr[-1][1], "final_gnorm_over_N": tr[-1][2] / N,
                      "traced_iterations": len(tr)}
+    rank = {"t": RANK_T, "reference": "each algorithm's own final traced iterate",
+            "kept_iterates": "ALS: sweeps 1-100, then every 10th; ALS-NCG: every iteration"}
+    for name, qs, r, ts in (("als", q_als, r_als, ta), ("als_ncg", q_ncg, r_ncg, tn)):
+        rank[name] = {"%.4g%%" % (100 * lv): {"iterations": r[lv], "seconds": ts.get(r[lv])}
+                      for lv in levels}
+        rank[name]["accuracy_at"] = {str(k): round(q, 6) for k, q in qs
+                                     if k in (1, 2, 5, 10, 20, 50, 100, 200, 500, 1000)}
+    rank["acceleration"] = {}
+    for lv in levels:
+        key = "%.4g%%" % (100 * lv)
+        a, b = rank["als"][key]["seconds"], rank["als_ncg"][key]["seconds"]
+        rank["acceleration"][key] = (a / b) if (a and b) else None
+    out["ranking_accuracy"] = rank
     for crit in ("f_tol", "g_tol"):
         a, b = out["als"]["seconds_to_" + crit], out["als_ncg"]["seconds_to_" + crit]
         e = out["als_ncg_exact_search"]["seconds_to_" + crit]
@@ -549,6 +620,8 @@ def main():
         "safeguards": solver.safeguards,
         "gnorm_over_N": solver.gnorm() / (P.n_f * (P.n_u + P.n_m)),
     }
+    result["ranking_kernels"] = ranking_kernels(DP, solver.x)
+    log("ranking kernels:", result["ranking_kernels"])
     fs = load_fstar()
     if not args.no_ttt and fs is not None and fs.get("problem", {}).get("csr_digest") == P.R.digest():
         ttt = time_to_tol(DP, P, fs["f_star"])

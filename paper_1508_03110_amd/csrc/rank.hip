@@ -13,8 +13,8 @@
 // ratings goes through LDS to a layout with four lanes per user.
 //
 // rank_top_kernel: every lane keeps a sorted list (best first) of the best
-// items among those it has seen (items q, q + 4, ... of each tile for lane
-// q of its user).  An item is inserted only if it is ahead of the t-th
+// items among those it has seen (items 16q .. 16q + 15 of each tile for
+// lane q of its user).  An item is inserted only if it is ahead of the t-th
 // entry of every one of the user's four lists (taken at the start of the
 // tile): a list holds t items ahead of anything behind its t-th entry.
 // At the end the four lists are merged through LDS.
@@ -38,7 +38,7 @@ namespace {
 constexpr int kRankUsers = 16;                 // users per wavefront (MFMA rows)
 constexpr int kRankWaves = 4;                  // wavefronts per workgroup
 constexpr int kRankItems = 64;                 // items per tile (4 MFMA column blocks)
-constexpr int kRankPitch = kRankItems + 1;     // LDS row pitch of the rating tile
+constexpr int kRankPitch = kRankItems + 2;     // LDS row pitch (16-byte rows, no bank conflicts)
 constexpr int kRankMaxT = 32;                  // largest t (list capacity)
 constexpr int kRankTQ = kRankMaxT / 4;         // reference items per lane (accuracy)
 
@@ -58,9 +58,9 @@ __device__ inline void wave_lds_sync() {
 }
 
 // A operand: lane (g, c) holds U[user0 + c][g*NS + s] for s < NS, zero past
-// n_f and for users past n_u (widened to FP64 at each MFMA).
-template <typename T, int NS>
-__device__ inline void load_users(T (&a)[NS], const T *U, int64_t n_u, int n_f, int ld,
+// n_f and for users past n_u, in type AT (T: widened to FP64 at each MFMA).
+template <typename T, typename AT, int NS>
+__device__ inline void load_users(AT (&a)[NS], const T *U, int64_t n_u, int n_f, int ld,
                                   int64_t user0) {
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     const int64_t u = user0 + c;
@@ -69,20 +69,18 @@ __device__ inline void load_users(T (&a)[NS], const T *U, int64_t n_u, int n_f, 
     for (int s = 0; s < NS; ++s) {
         const int k = g * NS + s;
         const T v = row[k < n_f ? k : n_f - 1];
-        a[s] = (u < n_u && k < n_f) ? v : T(0);
+        a[s] = (u < n_u && k < n_f) ? (AT)v : AT(0);
     }
 }
 
-// One 16x16 MFMA block of predicted ratings: D[u][c] = U[user0 + u] . M[item]
-// with `item` the item of lane column c (every lane passes the item of its
-// own column; 0 <= item < n_m).  Factors past n_f are read clamped and
-// cancelled by the zeros of the A operand.  VEC = 4: 16-byte loads (float
-// rows with n_f and ld multiples of 4 and a 16-byte aligned base).
+// B operand of one 16x16 MFMA block: lane (g, c) loads M[item][g*NS + s],
+// s < NS, for the item of its column c (0 <= item < n_m).  Factors past n_f
+// are read clamped and cancelled by the zeros of the A operand.  VEC = 4:
+// 16-byte loads (float rows with n_f and ld multiples of 4, aligned base).
 template <typename T, int NS, int VEC>
-__device__ inline dacc4 rating_block(const T (&a)[NS], const T *M, int item, int n_f, int ld) {
-    const int lane = threadIdx.x & 63, g = lane >> 4;
+__device__ inline void load_items(T (&b)[NS], const T *M, int item, int n_f, int ld) {
+    const int g = (threadIdx.x & 63) >> 4;
     const T *row = M + (int64_t)item * ld;
-    T b[NS];
     if constexpr (VEC == 4) {
         static_assert(NS % 4 == 0, "vector loads need NS % 4 == 0");
 #pragma unroll
@@ -101,26 +99,54 @@ __device__ inline dacc4 rating_block(const T (&a)[NS], const T *M, int item, int
             b[s] = row[k < n_f ? k : n_f - 1];
         }
     }
+}
+
+// D[u][c] = U[user0 + u] . M[item of column c], accumulated over the NS
+// steps in FP64.
+template <typename T, typename AT, int NS>
+__device__ inline dacc4 rating_mma(const AT (&a)[NS], const T (&b)[NS]) {
     dacc4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < NS; ++s) d = Mfma<double>::mma((double)a[s], (double)b[s], d);
     return d;
 }
 
-// Ratings of the wavefront's 16 users against items tile .. tile + 63 into
-// the LDS tile S[u * kRankPitch + x] (items past n_m repeat the last item;
-// readers skip them).
-template <typename T, int NS, int VEC>
-__device__ inline void rating_tile(const T (&a)[NS], const T *M, int n_m, int n_f, int ld,
-                                   int tile, double *S) {
+template <typename T, typename AT, int NS, int VEC>
+__device__ inline dacc4 rating_block(const AT (&a)[NS], const T *M, int item, int n_f, int ld) {
+    T b[NS];
+    load_items<T, NS, VEC>(b, M, item, n_f, ld);
+    return rating_mma<T, AT, NS>(a, b);
+}
+
+__device__ inline int tile_item(int tile, int b, int n_m) {
+    return min(tile + 16 * b + (threadIdx.x & 15), n_m - 1);
+}
+
+__device__ inline void store_block(double *S, int b, const dacc4 &d) {
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
 #pragma unroll
-    for (int b = 0; b < kRankItems / 16; ++b) {
-        const int item = min(tile + 16 * b + c, n_m - 1);
-        const dacc4 d = rating_block<T, NS, VEC>(a, M, item, n_f, ld);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) S[Mfma<double>::row(g, r) * kRankPitch + 16 * b + c] = d[r];
-    }
+    for (int r = 0; r < 4; ++r) S[Mfma<double>::row(g, r) * kRankPitch + 16 * b + c] = d[r];
+}
+
+// Ratings of the wavefront's 16 users against items tile .. tile + 63 into
+// the LDS tile S[u * kRankPitch + x] (items past n_m repeat the last item;
+// readers skip them).  Each block's loads are in flight while the previous
+// block's MFMAs run.  NEXT: b0 holds the B operand of the tile's first block
+// on entry and that of the next tile's first block on exit (loads in flight
+// across the caller's scan of the tile); else b0 is loaded here.
+template <typename T, typename AT, int NS, int VEC, bool NEXT>
+__device__ inline void rating_tile(const AT (&a)[NS], T (&b0)[NS], const T *M, int n_m, int n_f,
+                                   int ld, int tile, double *S) {
+    if constexpr (!NEXT) load_items<T, NS, VEC>(b0, M, tile_item(tile, 0, n_m), n_f, ld);
+    T b1[NS];
+    load_items<T, NS, VEC>(b1, M, tile_item(tile, 1, n_m), n_f, ld);
+    store_block(S, 0, rating_mma<T, AT, NS>(a, b0));
+    load_items<T, NS, VEC>(b0, M, tile_item(tile, 2, n_m), n_f, ld);
+    store_block(S, 1, rating_mma<T, AT, NS>(a, b1));
+    load_items<T, NS, VEC>(b1, M, tile_item(tile, 3, n_m), n_f, ld);
+    store_block(S, 2, rating_mma<T, AT, NS>(a, b0));
+    if constexpr (NEXT) load_items<T, NS, VEC>(b0, M, tile_item(tile + kRankItems, 0, n_m), n_f, ld);
+    store_block(S, 3, rating_mma<T, AT, NS>(a, b1));
 }
 
 // Insert (s, x) into the sorted list (ls, li) of capacity TT, dropping the
@@ -159,13 +185,13 @@ __global__ __launch_bounds__(kRankWaves * 64, (kTopOccupancy<T, NS, VEC>)) void 
                                                                    int64_t n_u, int n_m, int n_f,
                                                                    int ld, int t, int32_t *top) {
     constexpr int TT = kRankMaxT;
-    __shared__ double lds_all[kRankWaves][kTopLdsBytes / 8];
+    __shared__ __align__(16) double lds_all[kRankWaves][kTopLdsBytes / 8];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t user0 = ((int64_t)blockIdx.x * kRankWaves + w) * kRankUsers;
     if (user0 >= n_u) return;  // whole wavefront; no workgroup barrier below
     double *S = lds_all[w];
     T a[NS];
-    load_users<T, NS>(a, U, n_u, n_f, ld, user0);
+    load_users<T, T, NS>(a, U, n_u, n_f, ld, user0);
 
     const int u = lane >> 2, q = lane & 3;
     double ls[TT];
@@ -194,14 +220,32 @@ __global__ __launch_bounds__(kRankWaves * 64, (kTopOccupancy<T, NS, VEC>)) void 
                 bi = oi;
             }
         }
-        rating_tile<T, NS, VEC>(a, M, n_m, n_f, ld, tile, S);
+        T b0[NS];
+        rating_tile<T, T, NS, VEC, false>(a, b0, M, n_m, n_f, ld, tile, S);
         wave_lds_sync();
+        // lane q takes items 16q .. 16q + 15 of the tile: candidates first
+        // (16-byte reads), then the few insertions
         const int n_x = min(kRankItems, n_m - tile);
-#pragma unroll 1
-        for (int j = 0; j < kRankItems / 4; ++j) {
-            const int xl = q + 4 * j, x = tile + xl;
-            const double s = S[u * kRankPitch + xl];
-            if (xl < n_x && ahead(s, x, bs, bi)) list_insert<TT>(ls, li, s, x);
+        const double *row = S + u * kRankPitch + 16 * q;
+        unsigned cand = 0;
+        {
+            double v[16];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const double2 p = reinterpret_cast<const double2 *>(row)[i];
+                v[2 * i] = p.x;
+                v[2 * i + 1] = p.y;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (16 * q + i < n_x && ahead(v[i], tile + 16 * q + i, bs, bi)) cand |= 1u << i;
+        }
+        while (cand) {
+            const int i = __builtin_ctz(cand);
+            cand &= cand - 1;
+            const double s = row[i];
+            const int x = tile + 16 * q + i;
+            if (ahead(s, x, ls[TT - 1], li[TT - 1])) list_insert<TT>(ls, li, s, x);
         }
         wave_lds_sync();
     }
@@ -240,12 +284,17 @@ __global__ __launch_bounds__(kRankWaves * 64, (kTopOccupancy<T, NS, VEC>)) void 
     }
 }
 
+// Wavefronts per SIMD of the accuracy kernel (one where n_f > 64 and the
+// factors are FP64 or take element loads: no room for two without spills).
 template <typename T, int NS, int VEC>
-__global__ __launch_bounds__(kRankWaves * 64, 2) void rank_accuracy_kernel(
+constexpr int kAccOccupancy = (NS >= 28 && (sizeof(T) == 8 || VEC == 1)) ? 1 : 2;
+
+template <typename T, int NS, int VEC>
+__global__ __launch_bounds__(kRankWaves * 64, (kAccOccupancy<T, NS, VEC>)) void rank_accuracy_kernel(
     const T *U, const T *M, int64_t n_u, int n_m, int n_f, int ld, int t, const int32_t *top,
     int64_t *swaps, unsigned long long *total) {
     constexpr int TQ = kRankTQ;
-    __shared__ double S_all[kRankWaves][kRankUsers * kRankPitch];
+    __shared__ __align__(16) double S_all[kRankWaves][kRankUsers * kRankPitch];
     __shared__ double Th_all[kRankWaves][kRankUsers * kRankMaxT];
     __shared__ int Rk_all[kRankWaves][kRankUsers * kRankMaxT];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
@@ -253,15 +302,15 @@ __global__ __launch_bounds__(kRankWaves * 64, 2) void rank_accuracy_kernel(
     if (user0 >= n_u) return;  // whole wavefront; no workgroup barrier below
     double *S = S_all[w], *Th = Th_all[w];
     int *Rk = Rk_all[w];
-    T a[NS];
-    load_users<T, NS>(a, U, n_u, n_f, ld, user0);
+    double a[NS];
+    load_users<T, double, NS>(a, U, n_u, n_f, ld, user0);
 
     // ratings of the reference items: column c of block k holds a_k of user c
     {
         const int64_t uc = min(user0 + c, n_u - 1);
         for (int k = 0; k < t; ++k) {
             const int item = min(max(top[uc * t + k], 0), n_m - 1);
-            const dacc4 d = rating_block<T, NS, VEC>(a, M, item, n_f, ld);
+            const dacc4 d = rating_block<T, double, NS, VEC>(a, M, item, n_f, ld);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 if (Mfma<double>::row(g, r) == c) Th[c * kRankMaxT + k] = d[r];
@@ -283,17 +332,43 @@ __global__ __launch_bounds__(kRankWaves * 64, 2) void rank_accuracy_kernel(
         cnt[j] = 0;
         th_min = fmin(th_min, th[j]);
     }
+    // lowest reference rating of the user (over its four lanes)
+    th_min = fmin(th_min, __shfl_xor(th_min, 1));
+    th_min = fmin(th_min, __shfl_xor(th_min, 2));
+    T b0[NS];
+    load_items<T, NS, VEC>(b0, M, tile_item(0, 0, n_m), n_f, ld);
     for (int tile = 0; tile < n_m; tile += kRankItems) {
-        rating_tile<T, NS, VEC>(a, M, n_m, n_f, ld, tile, S);
+        rating_tile<T, double, NS, VEC, true>(a, b0, M, n_m, n_f, ld, tile, S);
         wave_lds_sync();
+        // items at or above the user's lowest reference rating: lane q scans
+        // items 16q .. 16q + 15 (16-byte reads), the four masks are combined,
+        // and every lane counts those few against its own reference items
         const int n_x = min(kRankItems, n_m - tile);
-        for (int xl = 0; xl < n_x; ++xl) {
-            const double s = S[u * kRankPitch + xl];
-            if (s >= th_min) {
-                const int x = tile + xl;
+        const double *row = S + u * kRankPitch;
+        unsigned long long cand;
+        {
+            double v[16];
 #pragma unroll
-                for (int j = 0; j < TQ; ++j) cnt[j] += (x != ak[j] && ahead(s, x, th[j], ak[j])) ? 1 : 0;
+            for (int i = 0; i < 8; ++i) {
+                const double2 p = reinterpret_cast<const double2 *>(row + 16 * q)[i];
+                v[2 * i] = p.x;
+                v[2 * i + 1] = p.y;
             }
+            unsigned m = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (16 * q + i < n_x && v[i] >= th_min) m |= 1u << i;
+            cand = (unsigned long long)m << (16 * q);
+            cand |= __shfl_xor(cand, 1);
+            cand |= __shfl_xor(cand, 2);
+        }
+        while (cand) {
+            const int xl = __builtin_ctzll(cand);
+            cand &= cand - 1;
+            const double s = row[xl];
+            const int x = tile + xl;
+#pragma unroll
+            for (int j = 0; j < TQ; ++j) cnt[j] += (x != ak[j] && ahead(s, x, th[j], ak[j])) ? 1 : 0;
         }
         wave_lds_sync();
     }
