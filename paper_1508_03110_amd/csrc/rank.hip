@@ -177,14 +177,15 @@ static_assert(kTopLdsBytes >= kRankUsers * kRankPitch * 8, "merge buffer covers 
 // Wavefronts per SIMD the top-t kernel is compiled for: two where the
 // register budget of two (256 per lane) holds the lists and the operands
 // without spills, else one.
-template <typename T, int NS, int VEC>
-constexpr int kTopOccupancy = (NS < 28 || (sizeof(T) == 4 && VEC == 4 && NS == 28)) ? 2 : 1;
+template <typename T, int NS, int VEC, int TT>
+constexpr int kTopOccupancy =
+    (NS < 28 || (sizeof(T) == 4 && VEC == 4 && (NS == 28 || TT <= 20))) ? 2 : 1;
 
-template <typename T, int NS, int VEC>
-__global__ __launch_bounds__(kRankWaves * 64, (kTopOccupancy<T, NS, VEC>)) void rank_top_kernel(const T *U, const T *M,
-                                                                   int64_t n_u, int n_m, int n_f,
-                                                                   int ld, int t, int32_t *top) {
-    constexpr int TT = kRankMaxT;
+// TT: list capacity (>= t; 20, the paper's t, or kRankMaxT).
+template <typename T, int NS, int VEC, int TT>
+__global__ __launch_bounds__(kRankWaves * 64, (kTopOccupancy<T, NS, VEC, TT>)) void rank_top_kernel(
+    const T *U, const T *M, int64_t n_u, int n_m, int n_f, int ld, int t, int32_t *top) {
+    static_assert(TT <= kRankMaxT, "merge buffer holds kRankMaxT entries per list");
     __shared__ __align__(16) double lds_all[kRankWaves][kTopLdsBytes / 8];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t user0 = ((int64_t)blockIdx.x * kRankWaves + w) * kRankUsers;
@@ -422,14 +423,16 @@ inline int64_t rank_blocks(int64_t n_u) {
     return (n_u + per - 1) / per;
 }
 
-template <typename T, int NS, int VEC> struct TopLaunch {
-    static int run(const void *U, const void *M, int64_t n_u, int n_m, int n_f, int ld, int t,
-                   int32_t *top, hipStream_t s) {
-        hipLaunchKernelGGL((rank_top_kernel<T, NS, VEC>), dim3((unsigned)rank_blocks(n_u)),
-                           dim3(kRankWaves * 64), 0, s, (const T *)U, (const T *)M, n_u, n_m, n_f,
-                           ld, t, top);
-        return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
-    }
+template <int TT> struct TopLaunch {
+    template <typename T, int NS, int VEC> struct L {
+        static int run(const void *U, const void *M, int64_t n_u, int n_m, int n_f, int ld, int t,
+                       int32_t *top, hipStream_t s) {
+            hipLaunchKernelGGL((rank_top_kernel<T, NS, VEC, TT>), dim3((unsigned)rank_blocks(n_u)),
+                               dim3(kRankWaves * 64), 0, s, (const T *)U, (const T *)M, n_u, n_m,
+                               n_f, ld, t, top);
+            return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+        }
+    };
 };
 
 template <typename T, int NS, int VEC> struct AccLaunch {
@@ -447,15 +450,23 @@ bool rank_vec4(const void *M, int n_f, int ld, als_dtype dt) {
     return dt == ALS_F32 && n_f % 4 == 0 && ld % 4 == 0 && ((uintptr_t)M & 15) == 0;
 }
 
+template <int TT>
+int launch_rank_top_tt(const void *U, const void *M, int64_t n_u, int n_m, int n_f, int ld,
+                       als_dtype dt, int t, int32_t *top, hipStream_t s) {
+    if (dt == ALS_F64)
+        return dispatch_ns<TopLaunch<TT>::template L, double, 1>(n_f, U, M, n_u, n_m, n_f, ld, t, top, s);
+    if (rank_vec4(M, n_f, ld, dt))
+        return dispatch_ns<TopLaunch<TT>::template L, float, 4>(n_f, U, M, n_u, n_m, n_f, ld, t, top, s);
+    return dispatch_ns<TopLaunch<TT>::template L, float, 1>(n_f, U, M, n_u, n_m, n_f, ld, t, top, s);
+}
+
 }  // namespace
 
 int launch_rank_top(const void *U, const void *M, int64_t n_u, int n_m, int n_f, int ld,
                     als_dtype dt, int t, int32_t *top, hipStream_t s) {
     if (n_u == 0) return ALS_OK;
-    if (dt == ALS_F64) return dispatch_ns<TopLaunch, double, 1>(n_f, U, M, n_u, n_m, n_f, ld, t, top, s);
-    if (rank_vec4(M, n_f, ld, dt))
-        return dispatch_ns<TopLaunch, float, 4>(n_f, U, M, n_u, n_m, n_f, ld, t, top, s);
-    return dispatch_ns<TopLaunch, float, 1>(n_f, U, M, n_u, n_m, n_f, ld, t, top, s);
+    if (t <= 20) return launch_rank_top_tt<20>(U, M, n_u, n_m, n_f, ld, dt, t, top, s);
+    return launch_rank_top_tt<kRankMaxT>(U, M, n_u, n_m, n_f, ld, dt, t, top, s);
 }
 
 int launch_rank_accuracy(Ctx *ctx, const void *U, const void *M, int64_t n_u, int n_m, int n_f,
