@@ -371,10 +371,16 @@ class NcgOracle:
     iteration, the line search is Algorithm 4 on the quartic of Section V-C.
     """
 
-    def __init__(self, R, Rt, n_f: int, lam: float):
+    def __init__(self, R, Rt, n_f: int, lam: float, alpha0: float = ALPHA0, tau: float = TAU,
+                 c: float = C_ARMIJO, max_trials: int = MAX_TRIALS, safeguard: bool = True,
+                 pr_plus: bool = False):
         self.R, self.Rt = _c(R), _c(Rt)
         self.n_u, self.n_m, self.n_f, self.lam = self.R.n_rows, self.R.n_cols, n_f, float(lam)
         self.nU = self.n_u * n_f
+        # Algorithm 4's constants (Section V-C: alpha_0 = 10, tau = 0.9, c = 0.5)
+        # and the trial cap of the safeguard reading
+        self.alpha0, self.tau, self.c, self.max_trials = float(alpha0), float(tau), float(c), int(max_trials)
+        self.safeguard, self.pr_plus = bool(safeguard), bool(pr_plus)
 
     def split(self, x):
         return x[: self.nU].reshape(self.n_u, self.n_f), x[self.nU:].reshape(self.n_m, self.n_f)
@@ -406,7 +412,7 @@ class NcgOracle:
         self.last_coeffs = C
         if C[1] >= 0.0:
             return None, 0, float("nan"), float(C[1])
-        alpha, n = backtrack(C)
+        alpha, n = backtrack(C, self.alpha0, self.tau, self.c, self.max_trials)
         fnew = float("nan") if alpha is None else float(np.polyval(C[::-1], alpha))
         return alpha, n, fnew, float(C[1])
 
@@ -414,6 +420,8 @@ class NcgOracle:
         return ncg_init(self.join(U0, M0), self.P, self.grad)
 
     def step(self, s: NcgState, **kw) -> NcgState:
+        kw.setdefault("safeguard", self.safeguard)
+        kw.setdefault("pr_plus", self.pr_plus)
         return ncg_step(s, self.P, self.grad, self.line_search, **kw)
 
 

@@ -342,6 +342,173 @@ def test_als_ncg_decreases_f_and_q_matches_f(c0):
     assert f_prev < fa[0]
 
 
+# ---------------------------------------------------------------- safeguards of Algorithm 2
+
+# The paper says nothing about a line search that fails or a direction that
+# is not a descent direction.  The reading taken here: when g^T p >= 0 or the
+# search fails, p is reset to -gbar_k and the search is run again (a
+# restart); if that fails too, the ALS point x_{k+1} = P(x_k) is taken and the
+# next direction restarts (beta = 0).  Each pin below compares ncg_step with
+# quantities formed separately: P from oracle.als_sweep, g from
+# oracle.gradient, steps from oracle.quartic and oracle.backtrack.
+
+def _ncg_parts(P):
+    o = oracle.NcgOracle(P.R, P.Rt, P.n_f, P.lam)
+
+    def als_point(x):
+        _, M = o.split(x)
+        U2, M2 = oracle.als_sweep(P.R, P.Rt, M, P.lam)
+        return o.join(U2, M2)
+
+    def grad(x):
+        U, M = o.split(x)
+        return o.join(*oracle.gradient(P.R, P.Rt, U, M, P.lam))
+    return o, als_point, grad
+
+
+def _advanced_state(o, P, k=3):
+    """An ALS-NCG state a few iterations in, so beta and p are generic."""
+    s = o.init(P.U0, P.M0)
+    for _ in range(k):
+        o.step(s)
+    assert s.safeguards == 0
+    return s
+
+
+def test_safeguard_failed_search_takes_the_als_point(c0):
+    """A line search that never accepts: the step must restart once, then take
+    x_{k+1} = P(x_k) (the ALS iteration, formed here by its own call), and the
+    next direction must be -gbar_{k+1} exactly (beta reset), with
+    gbar_{k+1} = x_{k+1} - P(x_{k+1})."""
+    o, als_point, grad = _ncg_parts(c0)
+    s = _advanced_state(o, c0)
+    x_k = s.x.copy()
+    r0 = s.restarts
+    calls = []
+
+    def never(x, p):
+        calls.append(p.copy())
+        return None, 400, float("nan"), float(grad(x) @ p)
+
+    oracle.ncg_step(s, o.P, o.grad, never)
+    assert len(calls) == 2                                 # first search, then the restarted one
+    np.testing.assert_array_equal(calls[1], -(x_k - als_point(x_k)))  # restart on -gbar_k
+    assert (s.restarts - r0, s.safeguards) == (1, 1)
+    assert rel(s.x, als_point(x_k)) <= 1e-15
+    gbar_new = s.x - als_point(s.x)
+    assert rel(s.p, -gbar_new) <= 1e-15                     # beta = 0 after the ALS point
+    assert rel(s.g, grad(s.x)) <= 1e-15
+    assert math.isnan(s.alpha) and math.isnan(s.f)
+    # f does not increase: the ALS point minimises each block in turn
+    assert o.f(s.x) <= o.f(x_k)
+
+
+def test_safeguard_ascent_direction_is_restarted_on_minus_gbar(c0):
+    """A direction with g^T p > 0 is replaced by -gbar_k before any step is
+    taken: with a line search that accepts any direction at a fixed alpha,
+    x_{k+1} = x_k - alpha gbar_k (not x_k + alpha p_k), one restart, no ALS
+    point, and beta of Eq. (8) is kept for the next direction."""
+    o, als_point, grad = _ncg_parts(c0)
+    s = _advanced_state(o, c0)
+    x_k, g_k = s.x.copy(), grad(s.x)
+    r0 = s.restarts
+    gbar_k = x_k - als_point(x_k)
+    s.p = g_k.copy()                                         # ascent: g^T p = ||g||^2 > 0
+    alpha = 0.37
+
+    def fixed(x, p):
+        return alpha, 0, float("nan"), float(grad(x) @ p)
+
+    oracle.ncg_step(s, o.P, o.grad, fixed)
+    assert (s.restarts - r0, s.safeguards) == (1, 0)
+    assert rel(s.x, x_k - alpha * gbar_k) <= 1e-15
+    gbar_new = s.x - als_point(s.x)
+    g_new = grad(s.x)
+    beta = float(gbar_new @ (g_new - g_k)) / float(gbar_k @ g_k)
+    assert beta != 0.0
+    assert rel(s.p, -gbar_new + beta * (-gbar_k)) <= 1e-13
+
+
+def test_safeguard_restart_still_ascent_takes_the_als_point(c0):
+    """When -gbar_k is not a descent direction either (a line search that
+    reports g^T p >= 0 for everything), the ALS point is taken."""
+    o, als_point, grad = _ncg_parts(c0)
+    s = _advanced_state(o, c0)
+    x_k = s.x.copy()
+    r0 = s.restarts
+
+    def uphill(x, p):
+        return 1.0, 0, float("nan"), 1.0
+
+    oracle.ncg_step(s, o.P, o.grad, uphill)
+    assert (s.restarts - r0, s.safeguards) == (1, 1)
+    assert rel(s.x, als_point(x_k)) <= 1e-15
+    assert rel(s.p, -(s.x - als_point(s.x))) <= 1e-15
+
+
+def test_safeguard_first_search_fails_restart_succeeds(c0):
+    """Backtracking with a cap too small for the first direction: the restarted
+    search on -gbar_k is Algorithm 4 on the quartic along -gbar_k (formed by
+    oracle.quartic and oracle.backtrack here), and its step is taken."""
+    o, als_point, grad = _ncg_parts(c0)
+    s = _advanced_state(o, c0)
+    x_k = s.x.copy()
+    r0 = s.restarts
+    gbar_k = x_k - als_point(x_k)
+    U, M = o.split(x_k)
+    PU, PM = o.split(-gbar_k)
+    C = oracle.quartic(c0.R, U, M, PU, PM, c0.lam)
+    a_ref, n_ref = oracle.backtrack(C)
+    assert a_ref is not None
+    seen = []
+
+    def first_fails(x, p):
+        Ux, Mx = o.split(x)
+        Pu, Pm = o.split(p)
+        Cp = oracle.quartic(c0.R, Ux, Mx, Pu, Pm, c0.lam)
+        if not seen:
+            seen.append(1)
+            return None, 0, float("nan"), float(Cp[1])
+        a, n = oracle.backtrack(Cp)
+        return a, n, float(np.polyval(Cp[::-1], a)), float(Cp[1])
+
+    oracle.ncg_step(s, o.P, o.grad, first_fails)
+    assert (s.restarts - r0, s.safeguards) == (1, 0)
+    assert s.trials == n_ref
+    assert rel(s.x, x_k - a_ref * gbar_k) <= 1e-15
+
+
+def test_safeguards_along_a_run_with_a_tight_trial_cap():
+    """NcgOracle with alpha_0 = 1e3 and at most 60 trials (alpha >= 1e3 * 0.9^59
+    = 2.0): many first searches fail.  Every iteration must then either take an
+    Armijo step along p_k or -gbar_k, or the ALS point P(x_k); f never increases;
+    and the counters count exactly those events."""
+    P = synth.random_problem(80, 60, n_f=6, lam=0.05, seed=21, density=0.25, x0_sigma=0.5)
+    o = oracle.NcgOracle(P.R, P.Rt, P.n_f, P.lam, alpha0=1e3, max_trials=60)
+    _, als_point, grad = _ncg_parts(P)
+    s = o.init(P.U0, P.M0)
+    f_prev = o.f(s.x)
+    restarts = safeguards = 0
+    for _ in range(12):
+        x_k, p_k = s.x.copy(), s.p.copy()
+        gbar_k = x_k - als_point(x_k)
+        o.step(s)
+        f_now = o.f(s.x)
+        assert f_now <= f_prev * (1 + 1e-14)
+        if s.safeguards > safeguards:
+            assert rel(s.x, als_point(x_k)) <= 1e-15
+            restarts += 1
+            safeguards += 1
+        else:
+            d = p_k if s.restarts == restarts else -gbar_k
+            restarts = s.restarts
+            assert s.alpha == pytest.approx(1e3 * 0.9 ** s.trials, rel=1e-12)
+            assert rel(s.x, x_k + s.alpha * d) <= 1e-14
+        assert (s.restarts, s.safeguards) == (restarts, safeguards)
+        f_prev = f_now
+    assert restarts > 0 and safeguards > 0
+
+
 # ---------------------------------------------------------------- reduced precision
 
 def test_bf16_round_matches_torch_and_hand_values():
