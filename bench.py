@@ -66,11 +66,39 @@ def profiled_traffic():
     return None
 
 
-def cpu_baseline(P):
-    """The FP64 oracle timed on the host: one full ALS-NCG iteration (the loop
-    body of Algorithm 2: quartic pass, backtracking, x + alpha p, P(x) = two
-    half-sweeps, gradient, direction) on the same matrix, so its rate has the
-    unit and definition of `value` (2 nnz half-sweep ratings per iteration)."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu reports it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def row_sample(A, n_rows):
+    """Evenly spaced rows of a CSR (host arrays) as a CSR of their own."""
+    import numpy as np
+    from types import SimpleNamespace
+    rows = np.linspace(0, A.n_rows - 1, n_rows).astype(np.int64)
+    lo, hi = A.indptr[rows], A.indptr[rows + 1]
+    take = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+    indptr = np.concatenate([[0], np.cumsum(hi - lo)]).astype(np.int64)
+    return SimpleNamespace(n_rows=n_rows, n_cols=A.n_cols, indptr=indptr,
+                           indices=A.indices[take], values=A.values[take])
+
+
+def cpu_baseline(P, reps=3, sample_users=2000):
+    """The FP64 oracle timed on the host.
+
+    value: one full ALS-NCG iteration (the loop body of Algorithm 2: quartic
+    pass, backtracking, x + alpha p, P(x) = two half-sweeps, gradient,
+    direction) on the whole matrix, all threads, median of `reps` iterations
+    after one untimed iteration, in the unit and definition of `value`
+    (2 nnz half-sweep ratings per iteration).  one_thread / all_threads: the
+    oracle's U half-sweep over evenly spaced sampled users, median of `reps`,
+    at 1 thread and at all threads (half-sweep ratings per second)."""
     import numpy as np
 
     import oracle
@@ -81,13 +109,36 @@ def cpu_baseline(P):
     t = time.perf_counter()
     s = o.init(U0, M0)
     t_init = time.perf_counter() - t
-    t = time.perf_counter()
     o.step(s)
-    dt = time.perf_counter() - t
+    its = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        o.step(s)
+        its.append(time.perf_counter() - t)
+    dt = float(np.median(its))
+    S = row_sample(P.R, sample_users)
+
+    def sweep_rate(n_threads):
+        oracle.set_threads(n_threads)
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            oracle.half_sweep(S, M0, P.lam)
+            ts.append(time.perf_counter() - t)
+        return len(S.indices) / float(np.median(ts))
+
+    r_all = sweep_rate(threads)
+    r_one = sweep_rate(1)
+    oracle.set_threads(threads)
     return {"value": 2.0 * P.nnz / dt, "unit": "ratings/s", "cores": threads, "kind": "oracle",
-            "sample": "one ALS-NCG iteration of the FP64 oracle (Algorithm 2 loop body) on the "
-                      "full %d-rating matrix, n_f=%d: %.1f s (set-up P(x0), g(x0): %.1f s)"
-                      % (P.nnz, P.n_f, dt, t_init)}
+            "cpu": cpu_model(),
+            "sample": "FP64 oracle ALS-NCG iteration (Algorithm 2 loop body) on the full "
+                      "%d-rating matrix, n_f=%d, %d threads: median of %d = %.2f s (runs %s; "
+                      "one untimed iteration and set-up P(x0), g(x0) %.1f s before)"
+                      % (P.nnz, P.n_f, threads, reps, dt, [round(x, 2) for x in its], t_init),
+            "half_sweep_sample": "U half-sweep over %d evenly spaced users (%d ratings), "
+                                 "median of %d" % (sample_users, len(S.indices), reps),
+            "half_sweep_ratings_per_s": {"threads_%d" % threads: r_all, "threads_1": r_one}}
 
 
 def load_fstar():
@@ -173,11 +224,17 @@ def ranking_small(ctx, n_starts=20, gtol=1e-6, max_als=3000, max_ncg=1500):
             del keep
             ks = {lv: int(np.argmax(q >= lv)) + 1 for lv in levels}  # the last iterate has q = 1
             marks = sorted(set(ks.values()))
-            s = make()
-            if name == "als_ncg":
-                s.capture()
+            # the clock starts before the set-up (ALS-NCG: P(x0) and g(x0));
+            # capturing the graphs runs no iteration and is left out
             torch.cuda.synchronize()
             t0, secs = time.perf_counter(), {}
+            s = make()
+            if name == "als_ncg":
+                torch.cuda.synchronize()
+                t_cap = time.perf_counter()
+                s.capture()
+                torch.cuda.synchronize()
+                t0 += time.perf_counter() - t_cap
             for k in range(1, marks[-1] + 1):
                 s.sweep() if name == "als" else s.replay()
                 if k in marks:
@@ -265,12 +322,14 @@ def time_to_tol(DP, P, fstar, tol=1e-6, gtol=1e-6, max_als=2500, max_ncg=600):
     k_exact = crossing(trace_e)
 
     def timed(make, step, marks):
+        # the clock starts before make(): ALS-NCG's set-up (P(x0) and the
+        # gradient at x0) is part of its time, as is ALS's upload of x0
         marks = sorted({m for m in marks if m})
         if not marks:
             return {}
-        s = make()
         torch.cuda.synchronize()
         t = time.perf_counter()
+        s = make()
         got = {}
         for k in range(1, marks[-1] + 1):
             step(s)
@@ -503,6 +562,28 @@ def c2_bench(ctx, steps=5, als_steps=3):
     return out
 
 
+def speedup_vs_gnorm(g_ncg, g_als, ms_als, ms_ncg):
+    """The speedup curve of Section VI (Fig. 6) from two gradient-norm traces.
+
+    g_ncg[k-1], g_als[j-1]: (1/N)||g|| after ALS-NCG iteration k and ALS
+    iteration j.  For each ALS-NCG iteration k >= 2 the level is the mean of
+    the norms after iterations k-1 and k (a two-iteration moving average, which
+    smooths the non-monotone NCG trace); j is the first ALS iteration whose
+    norm is at or below that level, and the speedup is the time of j ALS
+    iterations over the time of k ALS-NCG iterations, j ms_als / (k ms_ncg).
+    When ALS never gets there within its trace, speedup is None and
+    speedup_at_least = len(g_als) ms_als / (k ms_ncg), a lower bound."""
+    n_als = len(g_als)
+    rows = []
+    for k in range(2, len(g_ncg) + 1):
+        level = 0.5 * (g_ncg[k - 1] + g_ncg[k - 2])
+        j = next((i + 1 for i, g in enumerate(g_als) if g <= level), None)
+        rows.append({"ncg_iteration": k, "gnorm_over_N": level, "als_iterations": j,
+                     "speedup": (j * ms_als) / (k * ms_ncg) if j else None,
+                     "speedup_at_least": None if j else (n_als * ms_als) / (k * ms_ncg)})
+    return rows
+
+
 def c2_speedup_curve(DP, U0, M0, ms_als, ms_ncg, n_ncg=25, n_als=100, log=None):
     """Speedup of ALS-NCG over ALS as a function of the normalised gradient
     norm, by the paper's method (Section VI, Fig. 6): for each ALS-NCG
@@ -528,14 +609,7 @@ def c2_speedup_curve(DP, U0, M0, ms_als, ms_ncg, n_ncg=25, n_als=100, log=None):
         als.sweep()
         g_als.append(DP.loss_and_gnorm(als.x)[1] / N)
     del als
-    rows = []
-    for k in range(2, n_ncg + 1):
-        level = 0.5 * (g_ncg[k - 1] + g_ncg[k - 2])
-        j = next((i + 1 for i, g in enumerate(g_als) if g <= level), None)
-        rows.append({"ncg_iteration": k, "gnorm_over_N": level, "als_iterations": j,
-                     "speedup": (j * ms_als) / (k * ms_ncg) if j else None,
-                     # ALS did not get there in n_als iterations: a lower bound
-                     "speedup_at_least": None if j else (n_als * ms_als) / (k * ms_ncg)})
+    rows = speedup_vs_gnorm(g_ncg, g_als, ms_als, ms_ncg)
     if log:
         log("C2 speedup curve (%.1f s):" % (time.perf_counter() - t0),
             [(r["ncg_iteration"], "%.2e" % r["gnorm_over_N"], r["als_iterations"],
@@ -588,6 +662,102 @@ def serve_bench(ctx, M_dev, P, rates=(10_000, 50_000, 200_000), duration=2.0, wa
     return out
 
 
+def _r(x, d=4):
+    """Round to d significant digits (None stays None)."""
+    if x is None or isinstance(x, (bool, int)):
+        return x
+    return float("%.*g" % (d, x))
+
+
+def compact(res, full_path):
+    """The one-line result: the headline keys plus a one-number summary of
+    every leg (the traces, curves and per-trial lists stay in the full file)."""
+    keep = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+            "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config", "roofline",
+            "cpu_baseline")
+    out = {k: res[k] for k in keep if k in res}
+    out["value"] = _r(out["value"], 6)
+    out["ms_per_step"] = _r(out["ms_per_step"], 6)
+    rl = dict(out["roofline"])
+    out["roofline"] = {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                          "kernel", "flops_per_launch", "launch_ms",
+                                          "algorithmic_bytes") if k in rl}
+    if "cpu_baseline" in out:
+        cb = out["cpu_baseline"]
+        out["cpu_baseline"] = dict(cb, value=_r(cb["value"]),
+                                   half_sweep_ratings_per_s={k: _r(v) for k, v in
+                                                             cb["half_sweep_ratings_per_s"].items()})
+    out["half_sweep_ratings_per_s"] = {k: _r(v) for k, v in res["half_sweep_ratings_per_s"].items()}
+    out["phase_ms"] = {k: _r(v) for k, v in res["phase_ms"].items()}
+    out["pass_hbm_gbs"] = {k: _r(v) for k, v in res["pass_hbm_gbs"].items()}
+    out["f"] = _r(res["f"], 12)
+    tt = res.get("time_to_tol")
+    if tt:
+        sm = {"f_gap_tol": tt["f_gap_tol"], "gnorm_over_N_tol": tt["gnorm_over_N_tol"]}
+        for name in ("als", "als_ncg", "als_ncg_exact_search"):
+            e = tt[name]
+            sm[name] = [e["iterations_to_f_tol"], _r(e["seconds_to_f_tol"]),
+                        e["iterations_to_g_tol"], _r(e["seconds_to_g_tol"])]
+        sm["columns"] = "iterations to f-gap, s, iterations to (1/N)||g||, s"
+        for k in ("speedup_f_tol", "speedup_g_tol", "speedup_exact_search_f_tol",
+                  "speedup_exact_search_g_tol"):
+            sm[k] = _r(tt.get(k))
+        ra = tt.get("ranking_accuracy")
+        if ra:
+            sm["ranking_top20_acceleration"] = {k: _r(v, 3) for k, v in ra["acceleration"].items()}
+        out["time_to_tol"] = sm
+    rs = res.get("ranking_accuracy_small")
+    if rs:
+        out["ranking_600x400_acceleration"] = {k: _r(v, 3) for k, v in rs["acceleration"].items()}
+    rk = res.get("ranking_kernels")
+    if rk:
+        out["ranking_kernels_ms"] = {"top_t": rk["top_t_ms"], "accuracy": rk["accuracy_ms"]}
+    fi = res.get("fold_in")
+    if fi:
+        out["fold_in_p99_ms"] = {r: _r(v["p99_ms"], 3)
+                                 for r, v in fi["continuous_batching"]["rates"].items()}
+        out["fold_in_p50_ms"] = {r: _r(v["p50_ms"], 3)
+                                 for r, v in fi["continuous_batching"]["rates"].items()}
+        out["fold_in_solves_per_s"] = {r: _r(v["solves_per_s"], 3)
+                                       for r, v in fi["continuous_batching"]["rates"].items()}
+        out["fold_in_baseline_p99_ms"] = {r: _r(v["p99_ms"], 3) for r, v in
+                                          fi["one_request_per_launch"]["rates"].items()}
+    c3 = res.get("reduced_precision")
+    if c3:
+        sm = {}
+        for nf in C3_NF:
+            d = c3.get(str(nf), {})
+            for form in ("fp32", "bf16_refined", "bf16"):
+                e = d.get(form)
+                if not e:
+                    continue
+                err = e.get("rel_f_err_vs_fp64")
+                sm["%s_nf%d" % (form, nf)] = {
+                    "ms_per_it": _r(e["ms_per_iteration"]),
+                    "rel_f_err": _r(err[-1], 3) if err else None,
+                    "max_abs_dU": _r(e.get("max_abs_factor_diff_vs_fp64"), 3),
+                    "rmse": _r(next((v for k, v in e.items() if k.startswith("heldout_rmse_after")
+                                     and k != "heldout_rmse_after_%d" % e.get(
+                                         "compared_after_iterations", -1)), None)),
+                    "s_to_g_tol": _r(e.get("seconds_to_g_tol"))}
+        out["reduced_precision"] = sm
+    c2 = res.get("scale_1e9")
+    if c2:
+        out["scale_1e9"] = {"als_ms_per_sweep": _r(c2["als"]["ms_per_sweep"]),
+                            "als_ncg_ms_per_iteration": _r(c2["als_ncg"]["ms_per_iteration"]),
+                            "als_ncg_ratings_per_s": _r(c2["als_ncg"]["ratings_per_s"]),
+                            "sweep_U_tflops": _r(c2["sweep_U_tflops_eager"]),
+                            "phase_ms": {k: _r(v) for k, v in
+                                         c2["als_ncg"]["phase_ms_eager_step"].items()}}
+        curve = c2.get("speedup_vs_gnorm", {}).get("curve", [])
+        if curve:
+            out["scale_1e9"]["speedup_vs_gnorm"] = [
+                [_r(r["gnorm_over_N"], 3), _r(r["speedup"], 3) if r["speedup"] else
+                 ">%s" % _r(r["speedup_at_least"], 3)] for r in curve[::4]]
+    out["full_results"] = os.path.relpath(full_path, ROOT) if full_path else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -598,7 +768,11 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-f-tolerance measurement")
     ap.add_argument("--no-c3", action="store_true", help="skip the reduced-precision measurement")
     ap.add_argument("--no-c2", action="store_true", help="skip the billion-rating measurement")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="measured seconds per arrival rate (after --serve-warmup)")
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
+    ap.add_argument("--full-json", default=os.path.join(ROOT, "gpurun_out", "bench_full.json"),
+                    help="where every leg's detailed results are written")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -662,7 +836,11 @@ def main():
     roofline = {"bound": "mfma", "kernel": "sweep_chunks_kernel<float,7> (U half-sweep, one launch)",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(),
-                "flops_per_launch": fU, "launch_ms": round(phases["sweep_U"], 4)}
+                "flops_per_launch": fU, "launch_ms": round(phases["sweep_U"], 4),
+                # ratings (id + value), row offsets, M read once, U written, X_at read,
+                # U block of the gradient written
+                "algorithmic_bytes": P.nnz * 8 + (P.n_u + 1) * 8 + P.n_m * P.n_f * 4
+                                     + 3 * P.n_u * P.n_f * 4}
     # streaming passes: algorithmic bytes (index+value per rating, factor rows read once, output)
     by_coef = P.nnz * 8 + (P.n_u + P.n_m) * P.n_f * 4 * 2 + (P.n_u + 1 + P.n_m + 1) * 8
     by_grad = P.nnz * 8 + (P.n_u + P.n_m) * P.n_f * 4 + P.n_m * P.n_f * 4 + (P.n_m + 1) * 8
@@ -707,7 +885,8 @@ def main():
         log("ranking accuracy, 600 x 400:", result["ranking_accuracy_small"])
     if not args.no_serve:
         M_dev = DP.M(solver.x)[:, : P.n_f].contiguous()
-        result["fold_in"] = serve_bench(ctx, M_dev, P, duration=args.serve_seconds)
+        result["fold_in"] = serve_bench(ctx, M_dev, P, duration=args.serve_seconds,
+                                        warm=args.serve_warmup)
         p99 = {r: v["p99_ms"] for r, v in result["fold_in"]["continuous_batching"]["rates"].items()}
         result["fold_in_p99_ms"] = p99
     if not args.no_c3:
@@ -723,7 +902,17 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         result["cpu_baseline"] = cpu_baseline(P)
-    print(json.dumps(result), flush=True)
+    full = args.full_json
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(full)), exist_ok=True)
+        with open(full, "w") as fh:
+            json.dump(result, fh, indent=1)
+        log("full results written to", full)
+    except OSError as e:
+        log("could not write %s: %s" % (full, e))
+        full = None
+    line = json.dumps(compact(result, full), separators=(",", ":"))
+    print(line, flush=True)
 
 
 if __name__ == "__main__":

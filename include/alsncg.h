@@ -207,9 +207,11 @@ ALS_API int linesearch_coeffs(als_ctx *ctx, const als_plan *plan_R, const als_cs
  * when it passes the sufficient-decrease test of Algorithm 4 with constant c.
  * trials_out (device int32, may be NULL): 0, or -1 (alpha_out = 0) when
  * coeffs[1] >= 0, Q has no minimiser on alpha > 0, or the test fails.
+ * q_out (device double, may be NULL): Q(alpha_out) = f(x + alpha p) by
+ * Horner's rule, no fused multiply-adds; NaN on failure.
  */
 ALS_API int ncg_linesearch_exact(als_ctx *ctx, const double *coeffs, double c, double *alpha_out,
-                                 int32_t *trials_out, void *stream);
+                                 int32_t *trials_out, double *q_out, void *stream);
 
 /*
  * Backtracking line search, Algorithm 4, evaluated on the device from the
@@ -219,10 +221,13 @@ ALS_API int ncg_linesearch_exact(als_ctx *ctx, const double *coeffs, double c, d
  * which is f(x + alpha p) - f(x) <= alpha c g^T p divided by alpha > 0.
  * alpha_out (device double): the step, or 0 when no trial passed or C1 >= 0
  * (not a descent direction); trials_out (device int32, may be NULL): n, or
- * -1 on failure.  Section V-C uses tau = 0.9, c = 0.5, alpha0 = 10.
+ * -1 on failure.  q_out (device double, may be NULL): Q(alpha) = f(x +
+ * alpha p) of the accepted step by Horner's rule, no fused multiply-adds;
+ * NaN on failure.  Section V-C uses tau = 0.9, c = 0.5, alpha0 = 10.
  */
 ALS_API int ncg_backtrack(als_ctx *ctx, const double *coeffs, double alpha0, double tau, double c,
-                  int max_trials, double *alpha_out, int32_t *trials_out, void *stream);
+                  int max_trials, double *alpha_out, int32_t *trials_out, double *q_out,
+                  void *stream);
 
 /*
  * x <- x + alpha p over n elements, alpha read from device memory (Algorithm

@@ -59,13 +59,13 @@ _SIGS = {
                           _vp]),
     "linesearch_coeffs": (_i, [_vp, _vp, _csrp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _vp,
                                _vp]),
-    "ncg_backtrack": (_i, [_vp, _vp, _d, _d, _d, _i, _vp, _vp, _vp]),
+    "ncg_backtrack": (_i, [_vp, _vp, _d, _d, _d, _i, _vp, _vp, _vp, _vp]),
     "ncg_axpy": (_i, [_vp, _i64, _vp, _vp, _vp, _i, _vp]),
     "ncg_axpby": (_i, [_vp, _i64, _d, _vp, _d, _vp, _i, _vp]),
     "ncg_direction": (_i, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp]),
     "ncg_linesearch_step": (_i, [_vp, _vp, _csrp, _csrp, _vp, _vp, _vp, _i, _i, _d, _i, _i, _d, _d,
                                  _d, _i, _vp, _vp]),
-    "ncg_linesearch_exact": (_i, [_vp, _vp, _d, _vp, _vp, _vp]),
+    "ncg_linesearch_exact": (_i, [_vp, _vp, _d, _vp, _vp, _vp, _vp]),
     "ncg_direction_dev": (_i, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
     "fold_in": (_i, [_vp, _vp, _i64, _i, _i, _d, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rank_top_t": (_i, [_vp, _vp, _vp, _i64, _i64, _i, _i, _i, _i, _vp, _vp]),
@@ -207,10 +207,12 @@ def linesearch_coeffs(ctx, plan_R, R: Csr, Rt: Csr, U, M, pU, pM, n_f, ld, lam, 
         int(n_f), int(ld), float(lam), int(dt), _ptr(coeffs), _stream(stream)))
 
 
-def ncg_backtrack(ctx, coeffs, alpha0, tau, c, max_trials, alpha_out, trials_out=None, stream=None):
+def ncg_backtrack(ctx, coeffs, alpha0, tau, c, max_trials, alpha_out, trials_out=None, q_out=None,
+                  stream=None):
     return _check("ncg_backtrack", load().ncg_backtrack(ctx, _ptr(coeffs), float(alpha0), float(tau),
                                                         float(c), int(max_trials), _ptr(alpha_out),
-                                                        _ptr(trials_out), _stream(stream)))
+                                                        _ptr(trials_out), _ptr(q_out),
+                                                        _stream(stream)))
 
 
 def ncg_axpy(ctx, n, x, p, alpha, dt, stream=None):
@@ -238,9 +240,10 @@ def ncg_linesearch_step(ctx, plan_R, R: Csr, Rt: Csr, x, p, gbar, n_f, ld, lam, 
         int(max_trials), _ptr(state), _stream(stream)))
 
 
-def ncg_linesearch_exact(ctx, coeffs, c, alpha_out, trials_out=None, stream=None):
+def ncg_linesearch_exact(ctx, coeffs, c, alpha_out, trials_out=None, q_out=None, stream=None):
     return _check("ncg_linesearch_exact", load().ncg_linesearch_exact(
-        ctx, _ptr(coeffs), float(c), _ptr(alpha_out), _ptr(trials_out), _stream(stream)))
+        ctx, _ptr(coeffs), float(c), _ptr(alpha_out), _ptr(trials_out), _ptr(q_out),
+        _stream(stream)))
 
 
 def ncg_direction_dev(ctx, n, x, xbar, g_new, g_old, p, scal, restart_flag, pr_plus, dt, stream=None):

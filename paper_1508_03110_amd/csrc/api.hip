@@ -314,20 +314,21 @@ int linesearch_coeffs(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, co
 }
 
 int ncg_backtrack(als_ctx *ctx, const double *coeffs, double alpha0, double tau, double c,
-                  int max_trials, double *alpha_out, int32_t *trials_out, void *stream) {
+                  int max_trials, double *alpha_out, int32_t *trials_out, double *q_out,
+                  void *stream) {
     if (!ctx || !coeffs || !alpha_out || !(alpha0 > 0.0) || !(tau > 0.0 && tau < 1.0) ||
         !(c > 0.0 && c < 1.0) || max_trials < 1)
         return ALS_E_INVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
-    return launch_backtrack(coeffs, alpha0, tau, c, max_trials, alpha_out, trials_out,
+    return launch_backtrack(coeffs, alpha0, tau, c, max_trials, alpha_out, trials_out, q_out,
                             (hipStream_t)stream);
 }
 
 int ncg_linesearch_exact(als_ctx *ctx, const double *coeffs, double c, double *alpha_out,
-                         int32_t *trials_out, void *stream) {
+                         int32_t *trials_out, double *q_out, void *stream) {
     if (!ctx || !coeffs || !alpha_out || !(c > 0.0 && c < 1.0)) return ALS_E_INVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
-    return launch_quartic_min(coeffs, c, alpha_out, trials_out, (hipStream_t)stream);
+    return launch_quartic_min(coeffs, c, alpha_out, trials_out, q_out, (hipStream_t)stream);
 }
 
 int ncg_axpy(als_ctx *ctx, int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,

@@ -178,7 +178,7 @@ int launch_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt,
                   const void *M, const void *pU, const void *pM, int n_f, int ld, double lambda,
                   als_dtype dt, double *coeffs, const double *pred, hipStream_t s);
 int launch_backtrack(const double *coeffs, double alpha0, double tau, double c, int max_trials,
-                     double *alpha_out, int32_t *trials_out, hipStream_t s);
+                     double *alpha_out, int32_t *trials_out, double *q_out, hipStream_t s);
 int launch_axpy(int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,
                 hipStream_t s);
 int launch_axpby(int64_t n, double a, const void *x, double b, void *y, als_dtype dt,
@@ -196,7 +196,7 @@ int launch_ls_restart_dir(int64_t n, void *p, const void *gbar, const double *st
 int launch_ls_final(double *state, int exact, double alpha0, double tau, double c, int max_trials,
                     hipStream_t s);
 int launch_quartic_min(const double *coeffs, double c, double *alpha_out, int32_t *trials_out,
-                       hipStream_t s);
+                       double *q_out, hipStream_t s);
 
 // Top-t rankings and ranking accuracy (rank.hip).
 int launch_rank_top(const void *U, const void *M, int64_t n_u, int n_m, int n_f, int ld,

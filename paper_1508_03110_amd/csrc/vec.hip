@@ -265,23 +265,33 @@ __device__ void quartic_min_search(const double *C, double c, double *alpha_out,
     }
 }
 
+// Q(alpha) = f(x + alpha p) by Horner from the highest coefficient, no
+// contraction (the same roundings as a plain evaluation on the host).
+__device__ double quartic_value(const double *C, double alpha) {
+#pragma clang fp contract(off)
+    return (((C[4] * alpha + C[3]) * alpha + C[2]) * alpha + C[1]) * alpha + C[0];
+}
+
 __global__ void quartic_min_kernel(const double *__restrict__ C, double c,
-                                   double *__restrict__ alpha_out, int32_t *__restrict__ trials_out) {
+                                   double *__restrict__ alpha_out, int32_t *__restrict__ trials_out,
+                                   double *__restrict__ q_out) {
     double a;
     int n;
     quartic_min_search(C, c, &a, &n);
     *alpha_out = a;
     if (trials_out) *trials_out = n;
+    if (q_out) *q_out = n < 0 ? NAN : quartic_value(C, a);
 }
 
 __global__ void backtrack_kernel(const double *__restrict__ C, double alpha0, double tau, double c,
                                  int max_trials, double *__restrict__ alpha_out,
-                                 int32_t *__restrict__ trials_out) {
+                                 int32_t *__restrict__ trials_out, double *__restrict__ q_out) {
     double a;
     int n;
     backtrack_search(C, alpha0, tau, c, max_trials, &a, &n);
     *alpha_out = a;
     if (trials_out) *trials_out = n;
+    if (q_out) *q_out = n < 0 ? NAN : quartic_value(C, a);
 }
 
 // ---------------------------------------------------------------- device-side step control
@@ -341,8 +351,7 @@ __global__ void ls_final_kernel(double *__restrict__ st, int exact, double alpha
     st[22] = safe ? -1.0 : (double)n;
     st[23] = restarted ? 1.0 : 0.0;
     st[24] = safe ? 1.0 : 0.0;
-    // Q(alpha) by Horner from the highest coefficient
-    st[25] = safe ? NAN : (((C[4] * alpha + C[3]) * alpha + C[2]) * alpha + C[1]) * alpha + C[0];
+    st[25] = safe ? NAN : quartic_value(C, alpha);
     st[26] += restarted ? 1.0 : 0.0;
     st[27] += safe ? 1.0 : 0.0;
     st[28] += 1.0;
@@ -359,15 +368,16 @@ void launch_sum_columns(const double *parts, int64_t rows, int cols, double *out
 }
 
 int launch_quartic_min(const double *coeffs, double c, double *alpha_out, int32_t *trials_out,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(quartic_min_kernel, dim3(1), dim3(1), 0, s, coeffs, c, alpha_out, trials_out);
+                       double *q_out, hipStream_t s) {
+    hipLaunchKernelGGL(quartic_min_kernel, dim3(1), dim3(1), 0, s, coeffs, c, alpha_out, trials_out,
+                       q_out);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 
 int launch_backtrack(const double *coeffs, double alpha0, double tau, double c, int max_trials,
-                     double *alpha_out, int32_t *trials_out, hipStream_t s) {
+                     double *alpha_out, int32_t *trials_out, double *q_out, hipStream_t s) {
     hipLaunchKernelGGL(backtrack_kernel, dim3(1), dim3(1), 0, s, coeffs, alpha0, tau, c,
-                       max_trials, alpha_out, trials_out);
+                       max_trials, alpha_out, trials_out, q_out);
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
 

@@ -2,8 +2,9 @@
 
 Device memory comes from PyTorch; every arithmetic step runs in the HIP
 library through the C ABI (``_lib``).  The host only sequences the calls
-and, once per ALS-NCG iteration, reads back 16 scalars (the quartic
-coefficients, the step, beta, norms) to take the line-search decisions.
+and, once per ALS-NCG iteration of step(), reads back 16 scalars (the
+quartic coefficients, the step and Q(step), beta, norms) to take the
+restart and safeguard decisions; step_device() takes them on the device.
 """
 from __future__ import annotations
 
@@ -26,6 +27,7 @@ S_DEN, S_BETA, S_GG, S_NUM = 0, 1, 2, 3
 S_COEF = 4          # 4..8: C0..C4
 S_ALPHA = 9
 S_F, S_GN = 10, 11  # ncg_gradient out2
+S_Q = 12            # Q(alpha) = f(x + alpha p) of the accepted step
 
 
 class Context:
@@ -334,17 +336,17 @@ class AlsNcg:
         t = self._mark("linesearch_coeffs")
         P.coeffs(P.U(self.x), P.M(self.x), P.U(self.pdir), P.M(self.pdir), coef)
         self._done(t)
+        alpha_d, q_d = self.scal[S_ALPHA:S_ALPHA + 1], self.scal[S_Q:S_Q + 1]
         if self.search == "exact":
-            L.ncg_linesearch_exact(P.ctx.handle, coef, self.c, self.scal[S_ALPHA:S_ALPHA + 1],
-                                   self.trials)
+            L.ncg_linesearch_exact(P.ctx.handle, coef, self.c, alpha_d, self.trials, q_d)
         else:
             L.ncg_backtrack(P.ctx.handle, coef, self.alpha0, self.tau, self.c, self.max_trials,
-                            self.scal[S_ALPHA:S_ALPHA + 1], self.trials)
+                            alpha_d, self.trials, q_d)
         host = self.scal.cpu().numpy()
         n = int(self.trials.cpu().item())
         C = host[S_COEF:S_COEF + 5].copy()
         alpha = float(host[S_ALPHA]) if n >= 0 else None
-        return C, alpha, n
+        return C, alpha, n, float(host[S_Q])
 
     # -- Algorithm 2
     def init(self, U0, M0):
@@ -356,11 +358,11 @@ class AlsNcg:
 
     def step(self):
         P = self.p
-        C, alpha, n = self._line_search()
+        C, alpha, n, q = self._line_search()
         if self.safeguard and (C[1] >= 0.0 or alpha is None):
             L.ncg_axpby(P.ctx.handle, P.N, -1.0, self.xbar, 0.0, self.pdir, P.dt)  # p = -gbar
             self.restarts += 1
-            C, alpha, n = self._line_search()
+            C, alpha, n, q = self._line_search()
         restart = False
         if alpha is None or (self.safeguard and C[1] >= 0.0):
             if not self.safeguard:
@@ -372,7 +374,7 @@ class AlsNcg:
         else:
             L.ncg_axpy(P.ctx.handle, P.N, self.x, self.pdir, self.scal[S_ALPHA:S_ALPHA + 1], P.dt)
             self.alpha = alpha
-            self.f = float(np.polyval(C[::-1], alpha))
+            self.f = q  # Q(alpha), evaluated on the device
         self.coef, self.n_trials = C, n
         self._precondition_and_gradient()
         self._direction(restart=restart)

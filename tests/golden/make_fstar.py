@@ -5,11 +5,12 @@ oracle/ and synth/, nothing else): ALS-NCG (Algorithm 2 with the backtracking
 line search of Section V-C) from the shared starting point x0 (the seeded
 U0, M0 rounded to FP32, the same point the FP32 GPU runs start from), run
 until f changes by less than `--rtol` relative over 10 iterations or
-`--max-iter` iterations.  f* is the smallest f seen.  The run checkpoints its
-state (--ckpt) every 5 iterations and resumes from it, and rewrites the JSON
-after every checkpoint with the current estimate and its convergence status.
+`--max-iter` iterations.  f* is the smallest f seen.  The JSON is rewritten
+every 5 iterations with the current estimate and its convergence status;
+with --ckpt FILE the state is also saved there every 5 iterations and a run
+resumes from it.
 
-Usage: python tests/golden/make_fstar.py [--threads 5] [--max-iter 600]
+Usage: python tests/golden/make_fstar.py [--threads 5] [--max-iter 600] [--ckpt FILE]
 """
 import argparse
 import json
@@ -34,7 +35,9 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--max-iter", type=int, default=600)
     ap.add_argument("--rtol", type=float, default=1e-13)
-    ap.add_argument("--ckpt", default=os.path.join(ROOT, "_work", "fstar_ckpt.npz"))
+    ap.add_argument("--ckpt", default=None,
+                    help="checkpoint file (.npz) to write every 5 iterations and resume from; "
+                         "none by default")
     args = ap.parse_args()
     threads = oracle.set_threads(args.threads)
     P = synth.c1_ml20m()
@@ -42,7 +45,7 @@ def main():
     M0 = P.M0.astype(np.float32).astype(np.float64)
     o = oracle.NcgOracle(P.R, P.Rt, P.n_f, P.lam)
     fs = []
-    if os.path.exists(args.ckpt):
+    if args.ckpt and os.path.exists(args.ckpt):
         z = np.load(args.ckpt)
         s = oracle.NcgState(x=z["x"], p=z["p"], g=z["g"], gbar=z["gbar"], xbar=z["xbar"],
                             k=int(z["k"]), restarts=int(z["restarts"]), safeguards=int(z["safeguards"]))
@@ -63,10 +66,11 @@ def main():
         print("iter %d f=%.15g alpha=%s trials=%d restarts=%d safeguards=%d (%.1fs)"
               % (s.k, fs[-1], s.alpha, s.trials, s.restarts, s.safeguards, time.time() - t0), flush=True)
         if s.k % 5 == 0 or converged or s.k >= args.max_iter:
-            os.makedirs(os.path.dirname(args.ckpt), exist_ok=True)
-            np.savez(args.ckpt + ".tmp.npz", x=s.x, p=s.p, g=s.g, gbar=s.gbar, xbar=s.xbar, k=s.k,
-                     restarts=s.restarts, safeguards=s.safeguards, fs=np.array(fs))
-            os.replace(args.ckpt + ".tmp.npz", args.ckpt)
+            if args.ckpt:
+                os.makedirs(os.path.dirname(os.path.abspath(args.ckpt)), exist_ok=True)
+                np.savez(args.ckpt + ".tmp.npz", x=s.x, p=s.p, g=s.g, gbar=s.gbar, xbar=s.xbar,
+                         k=s.k, restarts=s.restarts, safeguards=s.safeguards, fs=np.array(fs))
+                os.replace(args.ckpt + ".tmp.npz", args.ckpt)
             last10 = fs[-11:]
             rel = (max(last10) - min(last10)) / abs(min(last10)) if len(last10) > 1 else float("nan")
             with open(OUT + ".tmp", "w") as fh:

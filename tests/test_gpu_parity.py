@@ -241,20 +241,23 @@ def test_backtracking_matches_oracle_decisions(ctx):
     C = torch.zeros(5, dtype=torch.float64, device=ctx.torch_device)
     a = torch.zeros(1, dtype=torch.float64, device=ctx.torch_device)
     n = torch.zeros(1, dtype=torch.int32, device=ctx.torch_device)
+    q = torch.zeros(1, dtype=torch.float64, device=ctx.torch_device)
     for k in range(200):
         c = np.array([3.0, -abs(rng.normal()) * 10 ** rng.uniform(-3, 1), rng.normal(),
                       rng.normal() * 0.1, abs(rng.normal()) * 0.01])
         if k % 50 == 0:
             c[1] = abs(c[1])  # not a descent direction
         C.copy_(torch.as_tensor(c))
-        L.ncg_backtrack(ctx.handle, C, 10.0, 0.9, 0.5, 400, a, n)
+        L.ncg_backtrack(ctx.handle, C, 10.0, 0.9, 0.5, 400, a, n, q)
         alpha, trials = oracle.backtrack(c)
         if c[1] >= 0.0:  # not a descent direction: the device refuses (documented)
             alpha = None
         if alpha is None:
-            assert int(n.item()) == -1 and float(a.item()) == 0.0
+            assert int(n.item()) == -1 and float(a.item()) == 0.0 and math.isnan(q.item())
         else:
             assert int(n.item()) == trials and float(a.item()) == alpha
+            # Q(alpha) by Horner without contraction: the host's polyval, bit for bit
+            assert float(q.item()) == float(np.polyval(c[::-1], alpha))
 
 
 # ---------------------------------------------------------------- vector layer
@@ -394,13 +397,16 @@ def test_exact_quartic_minimiser_matches_oracle(ctx):
         cd = torch.as_tensor(C, dtype=torch.float64, device=dev)
         a = torch.zeros(1, dtype=torch.float64, device=dev)
         n = torch.zeros(1, dtype=torch.int32, device=dev)
-        L.ncg_linesearch_exact(ctx.handle, cd, 1e-4, a, n)
+        q = torch.zeros(1, dtype=torch.float64, device=dev)
+        L.ncg_linesearch_exact(ctx.handle, cd, 1e-4, a, n, q)
         ref = oracle.quartic_min(C, c=1e-4)
         if ref is None:
             assert int(n.item()) == -1 and float(a.item()) == 0.0, C
+            assert math.isnan(q.item()), C
         else:
             assert int(n.item()) == 0, C
             assert float(a.item()) == pytest.approx(ref, rel=1e-10), C
+            assert float(q.item()) == float(np.polyval(C[::-1], float(a.item()))), C
 
 
 def test_als_ncg_exact_search_lockstep(ctx, c0):
@@ -424,6 +430,45 @@ def test_als_ncg_exact_search_lockstep(ctx, c0):
         oracle.ncg_step(s, o.P, o.grad, exact_ls)
         assert gpu.f == pytest.approx(o.f(s.x), rel=1e-10), k
     assert gpu.safeguards == 0
+
+
+@pytest.mark.parametrize("mode", ["host", "device"])
+@pytest.mark.parametrize("problem,max_trials", [("c0", 60), ("c0", 64), ("random", 62)])
+def test_als_ncg_safeguards_lockstep_with_oracle(ctx, c0, mode, problem, max_trials):
+    """The restart and ALS-point branch of Algorithm 2 with Algorithm 4 (the
+    safeguard reading: p = -gbar when g^T p >= 0 or no trial passes, then the
+    ALS point P(x_k) with beta = 0 next), forced by alpha0 = 1e3 and a cap of
+    60-64 trials (smallest alpha 2.0-1.6), FP64, in lockstep with the
+    oracle run with the same constants: every iteration the same trial
+    count, restart and safeguard counters, x_k within 1e-10 and f(x_k)
+    within 1e-10 relative (both NaN on an ALS-point step).  With the cap 60
+    every restart also fails (8 ALS points on the planted problem); with 64
+    and 62 some restarted searches succeed.  step() decides on the host,
+    step_device() on the device."""
+    from paper_1508_03110_amd.solver import AlsNcg
+    P = c0 if problem == "c0" else synth.random_problem(80, 60, n_f=6, lam=0.05, seed=21,
+                                                         density=0.25, x0_sigma=0.5)
+    DP = dev_problem(ctx, P, torch.float64)
+    kw = dict(alpha0=1e3, max_trials=max_trials)
+    gpu = AlsNcg(DP, **kw).init(P.U0, P.M0)
+    o = oracle.NcgOracle(P.R, P.Rt, P.n_f, P.lam, **kw)
+    s = o.init(P.U0, P.M0)
+    for k in range(12):
+        if mode == "host":
+            gpu.step()
+        else:
+            gpu.step_device()
+            gpu.read_state()
+        o.step(s)
+        assert (gpu.restarts, gpu.safeguards) == (s.restarts, s.safeguards), k
+        xs = gpu.x.cpu().numpy()
+        assert np.linalg.norm(xs - s.x) <= 1e-10 * np.linalg.norm(s.x), k
+        if math.isnan(s.alpha):           # ALS point taken
+            assert math.isnan(gpu.f), k
+        else:
+            assert gpu.n_trials == s.trials, k
+            assert gpu.f == pytest.approx(o.f(s.x), rel=1e-10), k
+    assert s.restarts > 0 and s.safeguards > 0, (s.restarts, s.safeguards)
 
 
 # ---------------------------------------------------------------- device-side control, graphs
