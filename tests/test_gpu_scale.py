@@ -8,7 +8,13 @@
   the longest user, random items and the most-rated item, which is split
   over many chunks) are recomputed one by one by the FP64 oracle from the
   same FP32 inputs.  FP32 tolerance: 1e-4 relative per row.
+* At the 20M-rating shape (n_f = 100): sampled half-sweep rows the same way,
+  ten ALS-NCG iterations against the FP64 oracle's stored trajectory of f,
+  and one full coefficient pass and gradient against the oracle.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -16,6 +22,8 @@ torch = pytest.importorskip("torch")
 
 import oracle
 import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -104,13 +112,23 @@ def check_sampled(ctx, ip_u, ix_u, va_u, ip_m, ix_m, va_m, M0, U, M, n_u, n_m, n
         assert rel.max() <= tol, side
 
 
+@pytest.fixture(scope="module")
+def c1():
+    print("generating the 20M-rating problem", flush=True)
+    return synth.c1_ml20m()
+
+
+@pytest.fixture(scope="module")
+def c1_dev(ctx, c1):
+    from paper_1508_03110_amd.solver import DeviceProblem
+    return DeviceProblem(ctx, c1.R, c1.Rt, c1.n_f, c1.lam, torch.float32)
+
+
 @pytest.mark.timeout(300)
-def test_ml20m_shape_half_sweeps_sampled(ctx):
+def test_ml20m_shape_half_sweeps_sampled(ctx, c1, c1_dev):
     """The 20M-rating shape in the benchmark's launch configuration (default
     plans), including the most-rated item (137,241 ratings, split)."""
-    from paper_1508_03110_amd.solver import DeviceProblem
-    P = synth.c1_ml20m()
-    DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32)
+    P, DP = c1, c1_dev
     dev = ctx.torch_device
     M0 = torch.as_tensor(P.M0.astype(np.float32)).to(dev)
     U = torch.empty((P.n_u, P.n_f), dtype=torch.float32, device=dev)
@@ -121,3 +139,67 @@ def test_ml20m_shape_half_sweeps_sampled(ctx):
     check_sampled(ctx, DP.R.indptr, DP.R.indices, DP.R.values, DP.Rt.indptr, DP.Rt.indices,
                   DP.Rt.values, M0, U, M, P.n_u, P.n_m, P.n_f, P.lam, seed=8, n_users=24,
                   n_items=12)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("mode", ["host", "device"])
+def test_ml20m_shape_als_ncg_trajectory(ctx, c1, c1_dev, mode):
+    """Ten FP32 ALS-NCG iterations at the 20M-rating shape (default plans,
+    the benchmark's launch configuration) from the shared x0 (seeded U0, M0
+    rounded to FP32): f(x_k) within 1e-5 relative of the FP64 oracle's
+    trajectory from the same x0, stored by tests/golden/make_fstar.py from
+    the oracle alone.  The oracle restarts once (iteration 2: the first
+    direction is an ascent direction, g^T p = +6.4e9), so the restart path
+    runs at full size.  Its accepted Armijo tests over these iterations are
+    at least 2e-3 |g^T p| from the boundary, so no trial count flips in FP32."""
+    from paper_1508_03110_amd.solver import AlsNcg
+    ref = json.load(open(os.path.join(GOLDEN, "fstar_ml20m_shape.json")))
+    assert ref["problem"]["csr_digest"] == c1.R.digest()
+    traj = ref["f_trajectory"]
+    s = AlsNcg(c1_dev).init(c1.U0.astype(np.float32), c1.M0.astype(np.float32))
+    for k in range(1, 11):
+        if mode == "host":
+            s.step()
+        else:
+            s.step_device()
+            s.read_state()
+        print("iteration %d f %.10g oracle %.10g rel %.2e restarts %d" %
+              (k, s.f, traj[k], abs(s.f - traj[k]) / traj[k], s.restarts), flush=True)
+        assert s.f == pytest.approx(traj[k], rel=1e-5), k
+    assert s.restarts == 1 and s.safeguards == 0
+
+
+@pytest.mark.timeout(300)
+def test_ml20m_shape_full_passes(ctx, c1, c1_dev):
+    """One coefficient pass and one gradient (both blocks, f and ||g||^2) over
+    all 20,000,263 ratings in the default plans (8192-rating chunks, 315
+    split item rows) against the FP64 oracle on the same FP32 inputs:
+    coefficients within 1e-6 of the largest, gradient within 1e-5 relative
+    (Frobenius, per block), f and ||g||^2 within 1e-6 and 1e-5."""
+    P, DP = c1, c1_dev
+    dev = ctx.torch_device
+    rng = np.random.default_rng(77)
+    U0, M0 = P.U0.astype(np.float32), P.M0.astype(np.float32)
+    PU = rng.normal(0.0, 0.1, U0.shape).astype(np.float32)
+    PM = rng.normal(0.0, 0.1, M0.shape).astype(np.float32)
+    x, p = DP.pack(U0, M0), DP.pack(PU, PM)
+    C = torch.zeros(5, dtype=torch.float64, device=dev)
+    DP.coeffs(DP.U(x), DP.M(x), DP.U(p), DP.M(p), C)
+    g = DP.zeros()
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    DP.gradient(DP.U(x), DP.M(x), DP.U(g), DP.M(g), out)
+    torch.cuda.synchronize()
+    print("oracle passes", flush=True)
+    f64 = lambda a: a.astype(np.float64)  # noqa: E731
+    ref = oracle.quartic(P.R, f64(U0), f64(M0), f64(PU), f64(PM), P.lam)
+    Cg = C.cpu().numpy()
+    print("coefficients", Cg, ref, flush=True)
+    assert np.max(np.abs(Cg - ref)) <= 1e-6 * np.max(np.abs(ref))
+    gU, gM = oracle.gradient(P.R, P.Rt, f64(U0), f64(M0), P.lam)
+    f = oracle.loss(P.R, f64(U0), f64(M0), P.lam)
+    for got, want in ((DP.U(g), gU), (DP.M(g), gM)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want)
+    fg, gg = out.cpu().tolist()
+    assert fg == pytest.approx(f, rel=1e-6)
+    assert gg == pytest.approx(float(np.sum(gU ** 2) + np.sum(gM ** 2)), rel=1e-5)
