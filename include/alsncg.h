@@ -200,6 +200,28 @@ ALS_API int linesearch_coeffs(als_ctx *ctx, const als_plan *plan_R, const als_cs
                       int ld, double lambda, als_dtype dt, double *coeffs, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * coefficients as linesearch_coeffs, from the same kernels in the same order
+ * (bitwise equal results), with the per-chunk partial sums kept in a fixed
+ * scratch array of 2^22 doubles (32 MiB) that the library holds on every
+ * device it runs on until the process ends; no device memory is allocated
+ * or freed.  Plans of more than linesearch_coeffs_noalloc_max_chunks() chunks
+ * are refused with ALS_E_BUDGET (nothing is launched).  Every call on one
+ * device shares that device's array and the last call leaves its contents
+ * there: calls that overlap on one device (different streams, or different
+ * contexts on one device) race and must be ordered by the caller.  Other
+ * arguments, outputs and errors as linesearch_coeffs.
+ */
+ALS_API int linesearch_coeffs_noalloc(als_ctx *ctx, const als_plan *plan_R, const als_csr *R,
+                                      const als_csr *Rt, const void *U, const void *M,
+                                      const void *pU, const void *pM, int n_f, int ld,
+                                      double lambda, als_dtype dt, double *coeffs, void *stream);
+
+/* Largest plan (in row chunks) that linesearch_coeffs_noalloc accepts. */
+ALS_API size_t linesearch_coeffs_noalloc_max_chunks(void);
+
+/*
  * Exact line search on the same quartic (a stronger search than Algorithm 4,
  * like the one the paper's serial runs use): alpha_out = the global minimiser
  * over alpha > 0 of Q(alpha) = sum coeffs[n] alpha^n, from the real roots of

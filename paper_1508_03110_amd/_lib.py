@@ -59,6 +59,9 @@ _SIGS = {
                           _vp]),
     "linesearch_coeffs": (_i, [_vp, _vp, _csrp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _vp,
                                _vp]),
+    "linesearch_coeffs_noalloc": (_i, [_vp, _vp, _csrp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d,
+                                       _i, _vp, _vp]),
+    "linesearch_coeffs_noalloc_max_chunks": (ctypes.c_size_t, []),
     "ncg_backtrack": (_i, [_vp, _vp, _d, _d, _d, _i, _vp, _vp, _vp, _vp]),
     "ncg_axpy": (_i, [_vp, _i64, _vp, _vp, _vp, _i, _vp]),
     "ncg_axpby": (_i, [_vp, _i64, _d, _vp, _d, _vp, _i, _vp]),
@@ -205,6 +208,17 @@ def linesearch_coeffs(ctx, plan_R, R: Csr, Rt: Csr, U, M, pU, pM, n_f, ld, lam, 
     return _check("linesearch_coeffs", load().linesearch_coeffs(
         ctx, plan_R, ctypes.byref(R), ctypes.byref(Rt), _ptr(U), _ptr(M), _ptr(pU), _ptr(pM),
         int(n_f), int(ld), float(lam), int(dt), _ptr(coeffs), _stream(stream)))
+
+
+def linesearch_coeffs_noalloc(ctx, plan_R, R: Csr, Rt: Csr, U, M, pU, pM, n_f, ld, lam, dt, coeffs,
+                              stream=None):
+    return _check("linesearch_coeffs_noalloc", load().linesearch_coeffs_noalloc(
+        ctx, plan_R, ctypes.byref(R), ctypes.byref(Rt), _ptr(U), _ptr(M), _ptr(pU), _ptr(pM),
+        int(n_f), int(ld), float(lam), int(dt), _ptr(coeffs), _stream(stream)))
+
+
+def linesearch_coeffs_noalloc_max_chunks():
+    return int(load().linesearch_coeffs_noalloc_max_chunks())
 
 
 def ncg_backtrack(ctx, coeffs, alpha0, tau, c, max_trials, alpha_out, trials_out=None, q_out=None,

@@ -13,6 +13,13 @@
 
 namespace alsncg {
 
+// Fixed device scratch of linesearch_coeffs_noalloc: 2^22 doubles (32 MiB)
+// per device, alive until the process ends.  Host code never uses this name
+// as an address: als_ctx_create looks up its device address once, with the
+// device current, and keeps it in the context.
+constexpr size_t kScratchDoubles = size_t(1) << 22;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 void *Ctx::workspace(size_t bytes, hipStream_t stream, int *err) {
     if (bytes == 0) bytes = 256;
     if (bytes <= ws_bytes) return ws;
@@ -102,6 +109,13 @@ int als_ctx_create(als_ctx **out, int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cu = prop.multiProcessorCount;
+    void *sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(alsncg::scratch)) != hipSuccess || !sp) {
+        delete c;
+        return ALS_E_HIP;
+    }
+    c->scratch = (double *)sp;
+    c->scratch_doubles = alsncg::kScratchDoubles;
     *out = c;
     return ALS_OK;
 }
@@ -311,6 +325,24 @@ int linesearch_coeffs(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, co
     if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
     return launch_coeffs(ctx, plan_R, R, Rt, U, M, pU, pM, n_f, ld, lambda, dt, coeffs, nullptr,
                          (hipStream_t)stream);
+}
+
+int linesearch_coeffs_noalloc(als_ctx *ctx, const als_plan *plan_R, const als_csr *R,
+                              const als_csr *Rt, const void *U, const void *M, const void *pU,
+                              const void *pM, int n_f, int ld, double lambda, als_dtype dt,
+                              double *coeffs, void *stream) {
+    if (!ctx || !csr_ok(R) || !Rt || !Rt->indptr || !plan_matches(plan_R, R) || !U || !M ||
+        !pU || !pM || !coeffs || ld < n_f || !lambda_ok(lambda) || !dtype_ok(dt, n_f, false))
+        return ALS_E_INVAL;
+    if (Rt->n_rows != R->n_cols) return ALS_E_INVAL;
+    if (!ctx->scratch) return ALS_E_HIP;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    return launch_coeffs(ctx, plan_R, R, Rt, U, M, pU, pM, n_f, ld, lambda, dt, coeffs, nullptr,
+                         (hipStream_t)stream, ctx->scratch, ctx->scratch_doubles);
+}
+
+size_t linesearch_coeffs_noalloc_max_chunks(void) {
+    return (alsncg::kScratchDoubles - alsncg::kSumStageDoubles) / 5 - alsncg::kCoeffItemBlocks;
 }
 
 int ncg_backtrack(als_ctx *ctx, const double *coeffs, double alpha0, double tau, double c,

@@ -140,6 +140,10 @@ struct Ctx {
     int num_cu = 256;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // device address of the library's fixed scratch array on this context's
+    // device (looked up once at creation) and its size in doubles
+    double *scratch = nullptr;
+    size_t scratch_doubles = 0;
     // Returns workspace of at least `bytes` (grows; synchronises before freeing).
     void *workspace(size_t bytes, hipStream_t stream, int *err);
 };
@@ -174,9 +178,16 @@ int launch_to_bf16(int64_t n, const float *x, void *y, hipStream_t s);
 int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, const als_csr *Rt,
                     const void *U, const void *M, int n_f, int ld, double lambda, als_dtype dt,
                     void *gU, void *gM, double *out2, hipStream_t s);
+// Blocks of the item-regulariser kernel of the coefficient pass (one
+// partial each, after the per-chunk partials).
+constexpr int kCoeffItemBlocks = 512;
+// fixed != nullptr: use these fixed_doubles doubles of device memory for the
+// per-chunk partial sums instead of the context's workspace (ALS_E_BUDGET
+// when they do not fit; nothing is allocated).
 int launch_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const void *U,
                   const void *M, const void *pU, const void *pM, int n_f, int ld, double lambda,
-                  als_dtype dt, double *coeffs, const double *pred, hipStream_t s);
+                  als_dtype dt, double *coeffs, const double *pred, hipStream_t s,
+                  double *fixed = nullptr, size_t fixed_doubles = 0);
 int launch_backtrack(const double *coeffs, double alpha0, double tau, double c, int max_trials,
                      double *alpha_out, int32_t *trials_out, double *q_out, hipStream_t s);
 int launch_axpy(int64_t n, void *x, const void *p, const double *alpha, als_dtype dt,

@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256) void coeff_itemreg_kernel(const int64_t *__res
     }
 }
 
-constexpr int kItemBlocks = 512;
+constexpr int kItemBlocks = kCoeffItemBlocks;
 
 // Grid of a streaming-pass chunk kernel: one workgroup per chunk, or the
 // plan's persistent grid.
@@ -550,13 +550,19 @@ int run_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt, co
 template <typename T, int VEC, int NV, int L>
 int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const T *U,
                const T *M, const T *PU, const T *PM, int n_f, int ld, double lambda,
-               double *coeffs, const double *pred, hipStream_t s) {
+               double *coeffs, const double *pred, hipStream_t s, double *fixed,
+               size_t fixed_doubles) {
     if ((int64_t)L * (NV - 1) * VEC >= n_f || L * NV * VEC < n_f) return ALS_E_INVAL;  // see Cols
     const int64_t rows = pR->n_chunks + kItemBlocks;
-    int err = ALS_OK;
-    double *part =
-        (double *)ctx->workspace((size_t)(rows * 5 + kSumStageDoubles) * sizeof(double), s, &err);
-    if (!part) return err;
+    const size_t need = (size_t)(rows * 5 + kSumStageDoubles);
+    double *part = fixed;
+    if (fixed) {
+        if (need > fixed_doubles) return ALS_E_BUDGET;
+    } else {
+        int err = ALS_OK;
+        part = (double *)ctx->workspace(need * sizeof(double), s, &err);
+        if (!part) return err;
+    }
     if (pR->n_chunks) {
         // a predicated pass (launched in every iteration, needed only after a
         // restart) always takes a persistent grid, so that when it is off it
@@ -646,10 +652,12 @@ int launch_gradient(Ctx *ctx, const Plan *pR, const als_csr *R, const Plan *pRt,
 
 int launch_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, const void *U,
                   const void *M, const void *pU, const void *pM, int n_f, int ld, double lambda,
-                  als_dtype dt, double *coeffs, const double *pred, hipStream_t s) {
+                  als_dtype dt, double *coeffs, const double *pred, hipStream_t s, double *fixed,
+                  size_t fixed_doubles) {
 #define CA(T, VEC, NV, L)                                                                       \
     return run_coeffs<T, VEC, NV, L>(ctx, pR, R, Rt, (const T *)U, (const T *)M, (const T *)pU, \
-                                     (const T *)pM, n_f, ld, lambda, coeffs, pred, s)
+                                     (const T *)pM, n_f, ld, lambda, coeffs, pred, s, fixed,     \
+                                     fixed_doubles)
     ALS_PASS_DISPATCH(dt, n_f, vec4_ok(n_f, ld, {U, M, pU, pM}), CA);
 #undef CA
 }
