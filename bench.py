@@ -41,6 +41,19 @@ def sweep_flops(nnz, n_rows, n_f):
     return nnz * (n_f * (n_f + 1) + 2 * n_f) + n_rows * (n_f ** 3 / 3.0 + 2 * n_f ** 2)
 
 
+def sweep_flops_binned(counts, n_f, dual_max):
+    """Algorithmic flops of one half-sweep with length bins: rows of
+    1 <= n_i <= dual_max ratings in the dual form (symmetric K = Y_I Y_I^T
+    n_i (n_i + 1) n_f, Cholesky n_i^3 / 3, two triangular solves 2 n_i^2,
+    x = Y_I^T z 2 n_i n_f), the others as sweep_flops."""
+    import numpy as np
+    n = np.asarray(counts, dtype=np.float64)
+    prim = n * (n_f * (n_f + 1) + 2 * n_f) + (n_f ** 3 / 3.0 + 2 * n_f ** 2)
+    dual = n * (n + 1) * n_f + n ** 3 / 3.0 + 2 * n ** 2 + 2 * n * n_f
+    use = (n >= 1) & (n <= dual_max)
+    return float(np.where(use, dual, prim).sum())
+
+
 def kernel_source_hash():
     import hashlib
     m = hashlib.sha256()
@@ -552,8 +565,12 @@ def c2_bench(ctx, steps=5, als_steps=3):
                       "graph_replays": steps, "phase_ms_eager_step": {k: round(v, 3) for k, v in phases.items()},
                       "f": s.f, "gnorm_over_N": s.gnorm() / (n_f * (DP.n_u + DP.n_m)),
                       "restarts": s.restarts, "safeguards": s.safeguards, "iterations": s.k}
-    fU = sweep_flops(DP.R.nnz, DP.n_u, n_f)
+    counts_u = (DP.R.indptr[1:] - DP.R.indptr[:-1]).cpu().numpy()
+    fU = sweep_flops_binned(counts_u, n_f, out["tuning"]["U"]["best"]["dual_max"])
+    del counts_u
     out["sweep_U_tflops_eager"] = fU / (phases["sweep_U"] * 1e-3) / 1e12
+    out["sweep_U_tflops_eager_eq3_count"] = (sweep_flops(DP.R.nnz, DP.n_u, n_f)
+                                             / (phases["sweep_U"] * 1e-3) / 1e12)
     log("C2:", out["als"], out["als_ncg"])
     del s
     out["speedup_vs_gnorm"] = c2_speedup_curve(DP, x0_U, x0_M, ms_als, ms_ncg, log=log)
@@ -681,7 +698,7 @@ def compact(res, full_path):
     rl = dict(out["roofline"])
     out["roofline"] = {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
                                           "kernel", "flops_per_launch", "launch_ms",
-                                          "algorithmic_bytes") if k in rl}
+                                          "algorithmic_bytes", "frac_eq3_count") if k in rl}
     if "cpu_baseline" in out:
         cb = out["cpu_baseline"]
         out["cpu_baseline"] = dict(cb, value=_r(cb["value"]),
@@ -691,6 +708,8 @@ def compact(res, full_path):
     out["phase_ms"] = {k: _r(v) for k, v in res["phase_ms"].items()}
     out["pass_hbm_gbs"] = {k: _r(v) for k, v in res["pass_hbm_gbs"].items()}
     out["f"] = _r(res["f"], 12)
+    if "length_bins" in res:
+        out["dual_max"] = {k: v["dual_max"] for k, v in res["length_bins"].items()}
     tt = res.get("time_to_tol")
     if tt:
         sm = {"f_gap_tol": tt["f_gap_tol"], "gnorm_over_N_tol": tt["gnorm_over_N_tol"]}
@@ -747,6 +766,8 @@ def compact(res, full_path):
                             "als_ncg_ms_per_iteration": _r(c2["als_ncg"]["ms_per_iteration"]),
                             "als_ncg_ratings_per_s": _r(c2["als_ncg"]["ratings_per_s"]),
                             "sweep_U_tflops": _r(c2["sweep_U_tflops_eager"]),
+                            "dual_max": {k: v["best"].get("dual_max") for k, v in
+                                         c2.get("tuning", {}).items()},
                             "phase_ms": {k: _r(v) for k, v in
                                          c2["als_ncg"]["phase_ms_eager_step"].items()}}
         curve = c2.get("speedup_vs_gnorm", {}).get("curve", [])
@@ -806,6 +827,16 @@ def main():
     log("plans: R", infoR, "R^T", infoRt)
     U0 = P.U0.astype(np.float32)
     M0 = P.M0.astype(np.float32)
+    # length bins of the half-sweeps: the dual-form bound of each plan, by timing
+    from paper_1508_03110_amd import tune
+    x_t = DP.pack(U0, M0)
+    bins = {}
+    for side, Y, n in (("U", DP.M(x_t), P.n_u), ("M", DP.U(x_t), P.n_m)):
+        X_t = torch.empty((n, DP.ld), dtype=torch.float32, device=ctx.torch_device)
+        bins[side] = tune.tune_dual(DP, side, Y, X_t)
+        log("length bins %s: %s" % (side, bins[side]))
+        del X_t
+    del x_t
     # Every decision of an iteration (line search, restart, safeguard) is
     # taken on the device, so the iterations are queued back to back with no
     # host read in between; f and the step counters are read once at the end.
@@ -828,15 +859,21 @@ def main():
     solver.read_state()
     log("timed %d steps: %.3f ms/step, phases %s, f=%.10g" % (args.steps, ms_step, phases, solver.f))
 
-    fU = sweep_flops(P.nnz, P.n_u, P.n_f)
-    fM = sweep_flops(P.nnz, P.n_m, P.n_f)
+    # the work of the binned half-sweeps as executed (dual-form rows counted
+    # with their own, smaller, algorithmic work), and the Eq. (3) count
+    fU3 = sweep_flops(P.nnz, P.n_u, P.n_f)
+    fU = sweep_flops_binned(P.R.counts(), P.n_f, bins["U"]["best"]["dual_max"])
+    fM = sweep_flops_binned(P.Rt.counts(), P.n_f, bins["M"]["best"]["dual_max"])
     tU = phases["sweep_U"] * 1e-3
     tM = phases["sweep_M"] * 1e-3
     achieved = fU / tU / 1e12
-    roofline = {"bound": "mfma", "kernel": "sweep_chunks_kernel<float,7> (U half-sweep, one launch)",
+    roofline = {"bound": "mfma",
+                "kernel": "U half-sweep: sweep_chunks_kernel<float,7> + sweep_dual_kernel bins",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(),
                 "flops_per_launch": fU, "launch_ms": round(phases["sweep_U"], 4),
+                "eq3_flops_per_launch": fU3,
+                "frac_eq3_count": round(fU3 / tU / 1e12 / PEAK_FP32_TFLOPS, 4),
                 # ratings (id + value), row offsets, M read once, U written, X_at read,
                 # U block of the gradient written
                 "algorithmic_bytes": P.nnz * 8 + (P.n_u + 1) * 8 + P.n_m * P.n_f * 4
@@ -866,6 +903,8 @@ def main():
         "pass_hbm_gbs": {"linesearch": by_coef / (phases["linesearch"] * 1e-3) / 1e9,
                          "gradient_M": by_grad / (phases["gradient_M"] * 1e-3) / 1e9},
         "roofline": roofline,
+        "length_bins": {k: v["best"] for k, v in bins.items()},
+        "length_bin_trials": {k: v["trials"] for k, v in bins.items()},
         "f": solver.f,
         "restarts": solver.restarts,
         "safeguards": solver.safeguards,

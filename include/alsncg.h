@@ -116,8 +116,23 @@ ALS_API void als_plan_destroy(als_plan *plan);
  * partials).  Used by the tuner. */
 ALS_API int als_plan_set_grid(als_plan *plan, int64_t sweep_grid, int64_t pass_grid);
 /* Plan statistics: out[0]=n_rows, [1]=nnz, [2]=n_chunks, [3]=split rows,
- * [4]=split chunks, [5]=chunk size, [6]=longest row. */
-ALS_API int als_plan_info(const als_plan *plan, int64_t out[7]);
+ * [4]=split chunks, [5]=chunk size, [6]=longest row, [7]=rows in the
+ * dual-form bins. */
+ALS_API int als_plan_info(const als_plan *plan, int64_t out[8]);
+/* Length bins of the half-sweep (Eq. (3)): rows with 1 <= n_i <= max_len
+ * ratings (max_len <= 94; capped at the plan's chunk size so that they are
+ * whole rows) are solved by als_sweep in the dual form
+ *     x_i = Y_I^T (Y_I Y_I^T + lambda n_i I)^{-1} r_i,
+ * an n_i x n_i system instead of n_f x n_f, which for lambda > 0 is the same
+ * solution (push-through identity (A^T A + c I)^{-1} A^T = A^T (A A^T + c I)^{-1}).
+ * The rows are binned by ceil((n_i + 2) / 16), the number of 16-wide tiles
+ * of their system (one kernel instance per bin); the others keep the
+ * n_f x n_f form.  max_len = 0 (the default) turns the bins off; with
+ * lambda = 0 als_sweep ignores them (the primal system is then singular for
+ * n_i < n_f and is reported as not positive definite).  Reorders the
+ * plan's chunks on the host and device (synchronises the device first);
+ * results of every other call do not depend on the order.  Used by the tuner. */
+ALS_API int als_plan_set_dual(als_plan *plan, int64_t max_len);
 
 /* ---------------------------------------------------------------- hot path */
 

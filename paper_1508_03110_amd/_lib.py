@@ -52,6 +52,7 @@ _SIGS = {
     "als_plan_destroy": (None, [_vp]),
     "als_plan_set_grid": (_i, [_vp, _i64, _i64]),
     "als_plan_info": (_i, [_vp, ctypes.POINTER(_i64)]),
+    "als_plan_set_dual": (_i, [_vp, _i64]),
     "als_sweep": (_i, [_vp, _vp, _csrp, _vp, _vp, _i, _i, _d, _i, _vp, _vp, _vp, _vp]),
     "als_sweep_mixed": (_i, [_vp, _vp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _vp, _vp]),
     "als_to_bf16": (_i, [_vp, _i64, _vp, _vp, _vp]),
@@ -168,10 +169,15 @@ def als_plan_set_grid(plan, sweep_grid, pass_grid=0):
     return _check("als_plan_set_grid", load().als_plan_set_grid(plan, int(sweep_grid), int(pass_grid)))
 
 
+def als_plan_set_dual(plan, max_len):
+    return _check("als_plan_set_dual", load().als_plan_set_dual(plan, int(max_len)))
+
+
 def als_plan_info(plan) -> dict:
-    a = (_i64 * 7)()
+    a = (_i64 * 8)()
     _check("als_plan_info", load().als_plan_info(plan, a))
-    keys = ("n_rows", "nnz", "n_chunks", "split_rows", "split_chunks", "chunk", "max_row")
+    keys = ("n_rows", "nnz", "n_chunks", "split_rows", "split_chunks", "chunk", "max_row",
+            "dual_rows")
     return dict(zip(keys, [int(v) for v in a]))
 
 

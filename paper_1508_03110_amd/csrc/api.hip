@@ -65,6 +65,14 @@ static bool plan_matches(const Plan *p, const als_csr *R) {
 static bool lambda_ok(double lambda) { return lambda >= 0.0 && isfinite(lambda); }
 
 template <typename V>
+static int copy_in(V *dst, const std::vector<V> &src) {
+    if (src.empty()) return ALS_OK;
+    return hipMemcpy(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice) == hipSuccess
+               ? ALS_OK
+               : ALS_E_HIP;
+}
+
+template <typename V>
 static int upload(V **dst, const std::vector<V> &src) {
     *dst = nullptr;
     const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(V);
@@ -147,7 +155,7 @@ int als_plan_set_grid(als_plan *p, int64_t sweep_grid, int64_t pass_grid) {
     return ALS_OK;
 }
 
-int als_plan_info(const als_plan *p, int64_t out[7]) {
+int als_plan_info(const als_plan *p, int64_t out[8]) {
     if (!p || !out) return ALS_E_INVAL;
     out[0] = p->n_rows;
     out[1] = p->nnz;
@@ -156,6 +164,58 @@ int als_plan_info(const als_plan *p, int64_t out[7]) {
     out[4] = p->n_slots;
     out[5] = p->chunk;
     out[6] = p->max_row;
+    out[7] = p->n_dual;
+    return ALS_OK;
+}
+
+int als_plan_set_dual(als_plan *p, int64_t max_len) {
+    if (!p || max_len < 0 || max_len > alsncg::kDualMaxLen) return ALS_E_INVAL;
+    max_len = std::min<int64_t>(max_len, p->chunk);  // dual rows are whole rows
+    const size_t nc = p->h_row.size();
+    auto is_dual = [&](size_t k) {
+        return p->h_slot[k] < 0 && p->h_len[k] >= 1 && p->h_len[k] <= max_len;
+    };
+    // current order is (non-dual, then dual rows) each longest first; rebuild
+    // it as all chunks longest first, then move the new dual rows last
+    std::vector<size_t> order(nc);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return p->h_len[a] > p->h_len[b]; });
+    std::stable_partition(order.begin(), order.end(), [&](size_t k) { return !is_dual(k); });
+    std::vector<int32_t> row(nc), len(nc), slot(nc);
+    std::vector<int64_t> beg(nc);
+    int64_t n_dual = 0;
+    for (size_t k = 0; k < nc; ++k) {
+        row[k] = p->h_row[order[k]];
+        len[k] = p->h_len[order[k]];
+        slot[k] = p->h_slot[order[k]];
+        beg[k] = p->h_beg[order[k]];
+        n_dual += is_dual(order[k]) ? 1 : 0;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) return ALS_E_HIP;  // no launch may read the old order
+    int rc = copy_in(p->chunk_row, row);
+    if (rc == ALS_OK) rc = copy_in(p->chunk_begin, beg);
+    if (rc == ALS_OK) rc = copy_in(p->chunk_len, len);
+    if (rc == ALS_OK) rc = copy_in(p->chunk_slot, slot);
+    if (rc == ALS_OK && p->n_slots > 0) {
+        std::vector<int32_t> slot_chunk((size_t)p->n_slots, 0);
+        for (size_t k = 0; k < nc; ++k)
+            if (slot[k] >= 0) slot_chunk[(size_t)slot[k]] = (int32_t)k;
+        rc = copy_in(p->slot_chunk, slot_chunk);
+    }
+    if (rc != ALS_OK) return rc;
+    p->h_row.swap(row);
+    p->h_len.swap(len);
+    p->h_slot.swap(slot);
+    p->h_beg.swap(beg);
+    p->dual_max = max_len;
+    p->n_dual = n_dual;
+    for (int b = 0; b < 8; ++b) p->dual_first[b] = p->dual_count[b] = 0;
+    for (int64_t k = (int64_t)nc - n_dual; k < (int64_t)nc; ++k) {
+        const int b = (int)((p->h_len[(size_t)k] + 2 + 15) / 16);
+        if (p->dual_count[b] == 0) p->dual_first[b] = k;
+        ++p->dual_count[b];
+    }
     return ALS_OK;
 }
 
@@ -248,6 +308,12 @@ int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **ou
     if (rc == ALS_OK) rc = upload(&p->chunk_begin, cbeg2);
     if (rc == ALS_OK) rc = upload(&p->chunk_len, clen2);
     if (rc == ALS_OK) rc = upload(&p->chunk_slot, cslot2);
+    if (rc == ALS_OK) {
+        p->h_row = crow2;
+        p->h_len = clen2;
+        p->h_slot = cslot2;
+        p->h_beg = cbeg2;
+    }
     if (rc == ALS_OK) rc = upload(&p->split_row, srow);
     if (rc == ALS_OK) rc = upload(&p->split_slot0, sslot0);
     if (rc == ALS_OK) rc = upload(&p->split_nslot, snslot);

@@ -26,6 +26,7 @@ constexpr int kWave = 64;
 template <typename T> struct Mfma;
 
 template <> struct Mfma<float> {
+    static constexpr als_dtype kDtype = ALS_F32;
     typedef float acc4 __attribute__((ext_vector_type(4)));
     __device__ static inline acc4 mma(float a, float b, acc4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -36,6 +37,7 @@ template <> struct Mfma<float> {
 };
 
 template <> struct Mfma<double> {
+    static constexpr als_dtype kDtype = ALS_F64;
     typedef double acc4 __attribute__((ext_vector_type(4)));
     __device__ static inline acc4 mma(double a, double b, acc4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -133,7 +135,23 @@ struct Plan {
     // split chunks: slot -> index of its chunk in chunk order (may be null
     // for plans that are only used by the FP32/FP64 half-sweep)
     int32_t *slot_chunk = nullptr;
+    // dual-form bins of the half-sweep (als_plan_set_dual): whole rows of
+    // 1 <= n_i <= dual_max ratings are the last n_dual chunks, longest first;
+    // bin b (1 <= b <= kDualMaxBlocks) holds the rows with
+    // ceil((n_i + 2) / 16) = b, chunks dual_first[b] .. + dual_count[b] - 1
+    int64_t dual_max = 0, n_dual = 0;
+    int64_t dual_first[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t dual_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // host copies of the chunk arrays (in chunk order), kept to re-bin
+    std::vector<int32_t> h_row, h_len, h_slot;
+    std::vector<int64_t> h_beg;
 };
+
+// Largest dual system: kDualMaxBlocks tiles of 16 (rows of at most
+// 16 kDualMaxBlocks - 2 ratings: one slot for the right-hand side, one for
+// the gradient point).
+constexpr int kDualMaxBlocks = 6;
+constexpr int64_t kDualMaxLen = 16 * kDualMaxBlocks - 2;
 
 struct Ctx {
     int device = 0;
@@ -159,6 +177,12 @@ namespace alsncg {
 int launch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f,
                  int ld, double lambda, als_dtype dt, const void *X_at, void *grad_out,
                  int64_t *bad_row, hipStream_t s);
+// Dual-form half-sweep over the plan's dual bins (sweep_dual.hip): for each
+// row u = Y_I^T (Y_I Y_I^T + lambda n_i I)^{-1} r_i, the same solution as
+// Eq. (3) when lambda > 0.  Optional fused gradient as launch_sweep.
+int launch_sweep_dual(const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f, int ld,
+                      double lambda, als_dtype dt, const void *X_at, void *grad_out,
+                      int64_t *bad_row, hipStream_t s);
 int launch_fold_in(Ctx *ctx, const void *M, int n_f, int ld, double lambda, als_dtype dt,
                    int64_t n_req, const int64_t *indptr, const int32_t *items, const float *vals,
                    void *U_out, int32_t *status, hipStream_t s);

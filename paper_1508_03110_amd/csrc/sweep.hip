@@ -425,20 +425,29 @@ int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, 
         partial = (acc4 *)ctx->workspace((size_t)plan->n_slots * TR::NT * kWave * sizeof(acc4), s, &err);
         if (!partial) return err;
     }
-    if (plan->n_chunks > 0) {
+    // the plan's dual-form bins (the last n_dual chunks) go to their own
+    // kernels; with lambda = 0 every row keeps the n_f x n_f form
+    const bool dual = plan->n_dual > 0 && lambda > T(0) && !status;
+    const int64_t n_main = dual ? plan->n_chunks - plan->n_dual : plan->n_chunks;
+    if (n_main > 0) {
         if (plan->grid > 0)
             hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true, VEC>),
-                               dim3((unsigned)std::min<int64_t>(plan->grid, plan->n_chunks)),
+                               dim3((unsigned)std::min<int64_t>(plan->grid, n_main)),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
-                               lambda, plan->n_chunks, plan->chunk_row, plan->chunk_begin,
+                               lambda, n_main, plan->chunk_row, plan->chunk_begin,
                                plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
                                status, empty_status);
         else
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)plan->n_chunks),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)n_main),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
-                               lambda, plan->n_chunks, plan->chunk_row, plan->chunk_begin,
+                               lambda, n_main, plan->chunk_row, plan->chunk_begin,
                                plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
                                status, empty_status);
+    }
+    if (dual) {
+        const int rc = launch_sweep_dual(plan, R, Y, X, n_f, ld, (double)lambda, Mfma<T>::kDtype,
+                                         X_at, grad_out, bad_row, s);
+        if (rc != ALS_OK) return rc;
     }
     if (plan->n_split_rows > 0)
         hipLaunchKernelGGL((sweep_split_kernel<T, NB>), dim3((unsigned)plan->n_split_rows),

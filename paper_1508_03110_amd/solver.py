@@ -90,12 +90,21 @@ class DeviceCsr:
         return d
 
     def replan(self, chunk: int = 0, grid: int = 0, grid_pass: int = 0):
-        """Rebuild the row plan with another chunk size and set its launch grids."""
+        """Rebuild the row plan with another chunk size and set its launch
+        grids (the dual-form bins are kept)."""
         if self.plan:
             L.als_plan_destroy(self.plan)
             self.plan = None
         self.plan = L.als_plan_create(self.ctx.handle, self.csr, int(chunk))
         self.set_grid(grid, grid_pass)
+        if getattr(self, "dual_max", 0):
+            L.als_plan_set_dual(self.plan, self.dual_max)
+
+    def set_dual(self, max_len: int):
+        """Solve rows of 1..max_len ratings (max_len <= 94) in the dual form
+        of the half-sweep (an n_i x n_i system); 0 turns it off."""
+        L.als_plan_set_dual(self.plan, int(max_len))
+        self.dual_max = int(max_len)
 
     def set_grid(self, grid: int, grid_pass: int = 0):
         """Persistent grids of the half-sweep and of the streaming passes (0: one

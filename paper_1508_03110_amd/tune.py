@@ -7,11 +7,15 @@ both algorithms) over a small grid of launch shapes and keeps the fastest:
     plan's default (nnz / (8 x compute units), at most 8192);
   * sweep grid: one workgroup per chunk, or a persistent grid of k
     workgroups per compute unit striding over the chunks (longest first).
-With that plan it then picks the persistent grid of the orientation's
-streaming pass (coefficients for R, gradient for R^T), whose per-chunk work
-is small enough for workgroup dispatch to matter.
-Results do not depend on any of these choices (every chunk reduces into its
-own slot in a fixed order); only time does.
+With that plan it then picks the length bins of the half-sweep: rows of at
+most `dual_max` ratings take the dual form (an n_i x n_i system, one kernel
+instance per 16-wide tile count), the rest the n_f x n_f form; candidates
+0 (off) and 16 b - 2 for b = 1 .. 6 tiles.  Last it picks the persistent
+grid of the orientation's streaming pass (coefficients for R, gradient for
+R^T), whose per-chunk work is small enough for workgroup dispatch to matter.
+Results do not depend on the chunk or the grids (every chunk reduces into
+its own slot in a fixed order), only time does; the dual form reaches the
+same per-row solution by a different rounding path.
 """
 from __future__ import annotations
 
@@ -33,6 +37,25 @@ def _best_ms(fn, reps):
         torch.cuda.synchronize()
         best = min(best, a.elapsed_time(b))
     return best
+
+
+DUAL_CANDIDATES = (0, 14, 30, 46, 62, 78, 94)
+
+
+def tune_dual(DP, side: str, Y, X, reps: int = 3, candidates=DUAL_CANDIDATES) -> dict:
+    """Pick the dual-form length bound of one orientation's plan by timing its
+    half-sweep (Y: fixed side, X: output buffer); leaves the best one set."""
+    A = DP.R if side == "U" else DP.Rt
+    trials = []
+    for m in candidates:
+        if m > 0 and m > A.info()["chunk"]:
+            continue
+        A.set_dual(m)
+        trials.append({"dual_max": m, "dual_rows": A.info()["dual_rows"],
+                       "ms": round(_best_ms(lambda: DP.sweep(side, Y, X), reps), 4)})
+    best = min(trials, key=lambda t: t["ms"])
+    A.set_dual(best["dual_max"])
+    return {"best": best, "trials": trials}
 
 
 def tune(DP, x, reps: int = 2, chunk_factors=(1.0, 0.25), grids_per_cu=(0, 4, 8, 16),
@@ -63,6 +86,8 @@ def tune(DP, x, reps: int = 2, chunk_factors=(1.0, 0.25), grids_per_cu=(0, 4, 8,
                 trials.append({"chunk": chunk, "grid": gpc * n_cu, "ms": round(ms, 4)})
         best = min(trials, key=lambda t: t["ms"])
         A.replan(best["chunk"], best["grid"], 0)
+        dual = tune_dual(DP, side, Y, X, reps=reps)
+        best = dict(best, dual_max=dual["best"]["dual_max"], dual_ms=dual["best"]["ms"])
         if side == "U":  # the coefficient pass runs over R
             run = lambda: DP.coeffs(U, M, pU, pM, coef)  # noqa: E731
         else:            # the M-block gradient pass runs over R^T
@@ -75,7 +100,7 @@ def tune(DP, x, reps: int = 2, chunk_factors=(1.0, 0.25), grids_per_cu=(0, 4, 8,
         A.set_grid(best["grid"], pbest["grid_pass"])
         out[side] = {"best": dict(best, grid_pass=pbest["grid_pass"], pass_ms=pbest["ms"]),
                      "default_ms": trials[0]["ms"], "default_pass_ms": ptrials[0]["ms"],
-                     "trials": trials, "pass_trials": ptrials,
+                     "trials": trials, "dual_trials": dual["trials"], "pass_trials": ptrials,
                      "seconds": round(time.perf_counter() - t0, 2)}
         say("tuned %s: %s (default sweep %.3f ms, pass %.3f ms)"
             % (side, out[side]["best"], trials[0]["ms"], ptrials[0]["ms"]))
