@@ -57,22 +57,23 @@ def sweep_flops_binned(counts, n_f, dual_max):
 def kernel_source_hash():
     import hashlib
     m = hashlib.sha256()
-    for f in ("sweep.hip", "internal.h", "rowsolve.h"):
+    for f in ("sweep.hip", "sweep_dual.hip", "internal.h", "rowsolve.h"):
         with open(os.path.join(ROOT, "paper_1508_03110_amd", "csrc", f), "rb") as fh:
             m.update(fh.read())
     return m.hexdigest()[:16]
 
 
-def profiled_traffic():
-    """HBM bytes per U half-sweep launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def profiled_traffic(dual_max):
+    """HBM bytes per U half-sweep (all its launches) from the committed
+    rocprofv3 counter summary for this length bound, or None when the kernel
+    sources changed since it was taken or the bound was not profiled."""
     path = os.path.join(ROOT, "profiles", "sweep_chunks_f32_nf100_ml20m_shape.md")
     try:
         for line in open(path):
             line = line.strip()
             if line.startswith("TRAFFIC "):
                 d = json.loads(line[len("TRAFFIC "):])
-                if d.get("source_hash") == kernel_source_hash():
+                if d.get("source_hash") == kernel_source_hash() and d.get("dual_max") == dual_max:
                     return int(d["bytes"])
     except OSError:
         pass
@@ -794,6 +795,9 @@ def main():
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--full-json", default=os.path.join(ROOT, "gpurun_out", "bench_full.json"),
                     help="where every leg's detailed results are written")
+    ap.add_argument("--dual", default=None, metavar="U,M",
+                    help="fix the dual-form length bounds of the user and item plans instead of "
+                         "timing the candidates (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -831,9 +835,11 @@ def main():
     from paper_1508_03110_amd import tune
     x_t = DP.pack(U0, M0)
     bins = {}
-    for side, Y, n in (("U", DP.M(x_t), P.n_u), ("M", DP.U(x_t), P.n_m)):
+    fixed = [int(v) for v in args.dual.split(",")] if args.dual else None
+    for k, (side, Y, n) in enumerate((("U", DP.M(x_t), P.n_u), ("M", DP.U(x_t), P.n_m))):
         X_t = torch.empty((n, DP.ld), dtype=torch.float32, device=ctx.torch_device)
-        bins[side] = tune.tune_dual(DP, side, Y, X_t)
+        cands = (fixed[k],) if fixed else tune.DUAL_CANDIDATES
+        bins[side] = tune.tune_dual(DP, side, Y, X_t, candidates=cands)
         log("length bins %s: %s" % (side, bins[side]))
         del X_t
     del x_t
@@ -870,7 +876,8 @@ def main():
     roofline = {"bound": "mfma",
                 "kernel": "U half-sweep: sweep_chunks_kernel<float,7> + sweep_dual_kernel bins",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(),
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": profiled_traffic(bins["U"]["best"]["dual_max"]),
                 "flops_per_launch": fU, "launch_ms": round(phases["sweep_U"], 4),
                 "eq3_flops_per_launch": fU3,
                 "frac_eq3_count": round(fU3 / tU / 1e12 / PEAK_FP32_TFLOPS, 4),
