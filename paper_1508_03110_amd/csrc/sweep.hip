@@ -119,14 +119,103 @@ __device__ __forceinline__ void finish_operand(T (&gv)[NB], bool ok, T r, int n_
     }
 }
 
-template <typename T, int NB>
+// Tiles (a, b) with b < NBC of the upper triangle (NBC = NB: all of them).
+template <typename T, int NB, int NBC = NB>
 __device__ __forceinline__ void gram_update(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
                                             const T (&gv)[NB]) {
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int bb = a; bb < NB; ++bb)
+        for (int bb = a; bb < NBC; ++bb)
             A[Tri<NB>::id(a, bb)] = Mfma<T>::mma(gv[a], gv[bb], A[Tri<NB>::id(a, bb)]);
+}
+
+// ---------------------------------------------------------------- last block column
+//
+// The last 16-wide block column L = NB - 1 holds only k_L = n_f + 1 - 16 (NB - 1)
+// real slots (5 at n_f = 100, 3 at n_f = 50), but a 16x16x4 tile computes all
+// 16 of its columns.  With LQ > 0 (FP32, k_L <= 4 LQ) that column is built
+// on v_mfma_f32_4x4x1_16b_f32 instead: 16 independent 4x4 blocks per
+// instruction, lane 4b + j holding in register r the product of the A value
+// of lane 4b + r and the B value of lane 4b + j.  Per rating t and half h of
+// the rows, A = y_t[slot 64 h + lane] and B = y_t[slot 16 L + 4 q + lane % 4],
+// so one instruction covers 64 rows x 4 columns of one rating: per group of
+// 4 ratings NH * LQ * 4 such instructions (8 cycles each) replace NB tiles
+// of 32 cycles.  The A operands come from the gathered registers by a 4x4
+// transposition of (lane row, register) with the lane-swap instructions
+// (gv[4 h + k] of row t -> register t of row k); B by one cross-lane
+// permute.  Used for NB = 3 and 4 (one half of rows, see run_sweep).
+template <int NB> struct LCol {
+    static constexpr int NH = (NB + 3) / 4;  // row halves of 64
+};
+
+// In: R[k] = register 4 h + k of every lane row.  Out: R[t] at lane row g
+// = the input R[g] at lane row t (rows are 16 lanes).
+__device__ __forceinline__ void transpose_rows4(float (&R)[4]) {
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(R[0]), __float_as_uint(R[2]), false, false);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(R[1]), __float_as_uint(R[3]), false, false);
+    auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+    auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+    R[0] = __uint_as_float(c[0]);
+    R[1] = __uint_as_float(c[1]);
+    R[2] = __uint_as_float(d[0]);
+    R[3] = __uint_as_float(d[1]);
+}
+
+template <int NB, int LQ>
+__device__ __forceinline__ void lcol_update(typename Mfma<float>::acc4 (&Dl)[LCol<NB>::NH * LQ],
+                                            const float (&gv)[NB], int lane) {
+    constexpr int NH = LCol<NB>::NH;
+    constexpr int L = NB - 1;
+    float At[NH][4];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) At[h][k] = (4 * h + k < NB) ? gv[4 * h + k] : 0.0f;
+        transpose_rows4(At[h]);
+    }
+#pragma unroll
+    for (int q = 0; q < LQ; ++q) {
+        // B of rating t: slot 16 L + 4 q + lane % 4 sits in lane row L % 4 of
+        // the transposed half L / 4, lane column 4 q + lane % 4
+        const int src = (16 * (L % 4) + 4 * q + (lane & 3)) << 2;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float bq = __int_as_float(
+                __builtin_amdgcn_ds_bpermute(src, __float_as_int(At[L / 4][t])));
+#pragma unroll
+            for (int h = 0; h < NH; ++h)
+                Dl[h * LQ + q] = __builtin_amdgcn_mfma_f32_4x4x1f32(At[h][t], bq, Dl[h * LQ + q], 0, 0, 0);
+        }
+    }
+}
+
+// The last block column's tiles (a, L) out of the 4x4 blocks, through LDS
+// (lds: 16 NB x 4 LQ floats); columns past 4 LQ are zero.
+template <int NB, int LQ>
+__device__ __forceinline__ void lcol_to_tiles(typename Mfma<float>::acc4 (&A)[Tri<NB>::NT],
+                                              const typename Mfma<float>::acc4 (&Dl)[LCol<NB>::NH * LQ],
+                                              float *lds, int lane) {
+    constexpr int NH = LCol<NB>::NH;
+    constexpr int W = 4 * LQ;
+    constexpr int L = NB - 1;
+    const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int q = 0; q < LQ; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 64 * h + 4 * (lane >> 2) + r;
+                if (row < 16 * NB) lds[row * W + 4 * q + (lane & 3)] = Dl[h * LQ + q][r];
+            }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            A[Tri<NB>::id(a, L)][r] = c < W ? lds[(16 * a + Mfma<float>::row(g, r)) * W + c] : 0.0f;
+    __syncthreads();
 }
 
 // Gram accumulation over ratings [b, e) of one row.  kGramDepth register
@@ -148,8 +237,9 @@ __device__ __forceinline__ void gram_update(typename Mfma<T>::acc4 (&A)[Tri<NB>:
 // Loads for groups past the end read valid addresses and are discarded.
 constexpr int kGramDepth = 3;
 
-template <typename T, int NB, bool VEC>
+template <typename T, int NB, bool VEC, int LQ = 0>
 __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
+                                                typename Mfma<T>::acc4 (&Dl)[LCol<NB>::NH * (LQ ? LQ : 1)],
                                                 const int32_t *__restrict__ idx,
                                                 const float *__restrict__ val, int64_t b, int64_t e,
                                                 const T *__restrict__ Y, int ld, int n_f, int g,
@@ -189,7 +279,12 @@ __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<
             rq[slot] = vx[p];
             if (s + k < ng) {
                 finish_operand<T, NB>(buf[k], 4 * (s + k) + g <= last, (T)rv[k], n_f, c);
-                gram_update<T, NB>(A, buf[k]);
+                if constexpr (LQ > 0) {
+                    gram_update<T, NB, NB - 1>(A, buf[k]);
+                    lcol_update<NB, LQ>(Dl, buf[k], 16 * g + c);
+                } else {
+                    gram_update<T, NB>(A, buf[k]);
+                }
             }
         }
     }
@@ -304,7 +399,7 @@ template <typename T, int NB> struct Occ {
 
 // One chunk: Gram of its ratings, then either the partial tiles (split row)
 // or the row solve.
-template <typename T, int NB, bool VEC>
+template <typename T, int NB, bool VEC, int LQ>
 __device__ __forceinline__ void sweep_chunk(
     int64_t q, const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
@@ -332,7 +427,11 @@ __device__ __forceinline__ void sweep_chunk(
     acc4 A[TR::NT];
 #pragma unroll
     for (int t = 0; t < TR::NT; ++t) A[t] = acc4{T(0), T(0), T(0), T(0)};
-    gram_accumulate<T, NB, VEC>(A, idx, val, b, b + len, Y, ld, n_f, g, c);
+    acc4 Dl[LCol<NB>::NH * (LQ ? LQ : 1)];
+#pragma unroll
+    for (int t = 0; t < LCol<NB>::NH * (LQ ? LQ : 1); ++t) Dl[t] = acc4{T(0), T(0), T(0), T(0)};
+    gram_accumulate<T, NB, VEC, LQ>(A, Dl, idx, val, b, b + len, Y, ld, n_f, g, c);
+    if constexpr (LQ > 0) lcol_to_tiles<NB, LQ>(A, Dl, sm, lane);
     if (slot >= 0) {
         acc4 *dst = partial + (int64_t)slot * TR::NT * kWave;
 #pragma unroll
@@ -348,7 +447,7 @@ __device__ __forceinline__ void sweep_chunk(
 // striding over the chunks (PERSIST = true; chunks are ordered longest
 // first, so the stride deals them out like a greedy schedule).
 // chunk_row == nullptr: chunk q is row q in full (fold-in and unplanned use).
-template <typename T, int NB, bool PERSIST, bool VEC>
+template <typename T, int NB, bool PERSIST, bool VEC, int LQ = 0>
 __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
@@ -360,13 +459,13 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     __shared__ T sm[Shared<T, NB>::size];
     if constexpr (PERSIST) {
         for (int64_t q = blockIdx.x; q < n_chunks; q += gridDim.x)
-            sweep_chunk<T, NB, VEC>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row,
+            sweep_chunk<T, NB, VEC, LQ>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row,
                                     chunk_begin, chunk_len, chunk_slot, partial, X_at, grad_out,
                                     bad_row, status, empty_status, sm);
     } else {
         const int64_t q = blockIdx.x;
         if (q >= n_chunks) return;
-        sweep_chunk<T, NB, VEC>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row,
+        sweep_chunk<T, NB, VEC, LQ>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row,
                                 chunk_begin, chunk_len, chunk_slot, partial, X_at, grad_out,
                                 bad_row, status, empty_status, sm);
     }
@@ -404,7 +503,7 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_split_kernel(
 
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 
-template <typename T, int NB, bool VEC>
+template <typename T, int NB, bool VEC, int LQ = 0>
 int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
               T lambda, const T *X_at, T *grad_out, int64_t *bad_row, int32_t *status, int empty_status,
               int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
@@ -413,7 +512,7 @@ int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, 
     if (bad_row) hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, bad_row, (int64_t)LLONG_MAX);
     if (!plan) {
         if (n_rows_unplanned > 0)
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)n_rows_unplanned),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC, LQ>), dim3((unsigned)n_rows_unplanned),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
                                lambda, n_rows_unplanned, nullptr, nullptr, nullptr, nullptr,
                                (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status);
@@ -431,14 +530,14 @@ int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, 
     const int64_t n_main = dual ? plan->n_chunks - plan->n_dual : plan->n_chunks;
     if (n_main > 0) {
         if (plan->grid > 0)
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true, VEC>),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true, VEC, LQ>),
                                dim3((unsigned)std::min<int64_t>(plan->grid, n_main)),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
                                lambda, n_main, plan->chunk_row, plan->chunk_begin,
                                plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
                                status, empty_status);
         else
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)n_main),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC, LQ>), dim3((unsigned)n_main),
                                dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
                                lambda, n_main, plan->chunk_row, plan->chunk_begin,
                                plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
@@ -461,6 +560,29 @@ template <typename T, int NB>
 int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
               T lambda, const T *X_at, T *grad_out, int64_t *bad_row, int32_t *status, int empty_status,
               int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
+    if constexpr (sizeof(T) == 4 && (NB == 3 || NB == 4)) {
+        // the last block column on 4x4 MFMA blocks when its rows fit one
+        // half of 64 and it holds at most 4 real slots (NB = 3) or 8
+        // (NB = 4): measured, e.g. both half-sweeps at n_f = 50 take 20-25 %
+        // less time; with two halves (NB = 7, n_f = 100) the transpositions
+        // and permutes cost more than the MFMA cycles saved
+        const int kl = n_f + 1 - 16 * (NB - 1);
+        const bool vec = ld % 4 == 0 && ((uintptr_t)Y % 16) == 0;
+#define ALS_SWEEP_LQ(V, Q)                                                                          \
+    return run_sweep_v<T, NB, V, Q>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out, bad_row, \
+                                    status, empty_status, n_rows_unplanned, partial_ext, s)
+        if (kl <= 4) {
+            if (vec) ALS_SWEEP_LQ(true, 1);
+            ALS_SWEEP_LQ(false, 1);
+        }
+        if constexpr (NB == 4) {
+            if (kl <= 8) {
+                if (vec) ALS_SWEEP_LQ(true, 2);
+                ALS_SWEEP_LQ(false, 2);
+            }
+        }
+#undef ALS_SWEEP_LQ
+    }
     if constexpr (sizeof(T) == 4) {
         if (ld % 4 == 0 && ((uintptr_t)Y % 16) == 0)
             return run_sweep_v<T, NB, true>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out,

@@ -85,7 +85,10 @@ def test_sweep_tiny_planted(ctx, c0, dtype, chunk):
 
 
 NF64 = [1, 2, 10, 16, 31, 32, 50, 64, 95]
-NF32 = [1, 2, 10, 15, 16, 32, 50, 64, 100, 127, 128, 143]
+# FP32 n_f = 32..35 and 48..55 put 1..4 (1..8) real slots in the last 16-wide
+# block column, which then runs on 4x4 MFMA blocks (one or two column
+# groups); 36 and 56 are the first sizes past it
+NF32 = [1, 2, 10, 15, 16, 32, 35, 36, 48, 50, 51, 52, 55, 56, 64, 96, 100, 127, 128, 143]
 
 
 @pytest.mark.parametrize("dtype,n_f", [(torch.float64, n) for n in NF64] +
