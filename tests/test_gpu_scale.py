@@ -80,6 +80,20 @@ def test_billion_rating_half_sweeps_sampled(ctx):
     assert int(bad.item()) == (1 << 63) - 1
     check_sampled(ctx, R.indptr, R.indices, R.values, R.indptr_t, R.indices_t, R.values_t,
                   M0, U, M, DP.n_u, DP.n_m, 50, 0.05, seed=9, n_users=24, n_items=12)
+    # the benchmark's length bins (users with 1..46 ratings in the dual form,
+    # 9.2M rows in bins of 1..3 tiles) and one workgroup per chunk; users
+    # sampled among the short rows as well
+    DP.R.set_grid(0)
+    DP.Rt.set_grid(0)
+    DP.R.set_dual(46)
+    DP.Rt.set_dual(46)
+    print("dual rows", DP.R.info()["dual_rows"], DP.Rt.info()["dual_rows"], flush=True)
+    DP.sweep("U", M0, U, bad_row=bad)
+    DP.sweep("M", U, M, bad_row=bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == (1 << 63) - 1
+    check_sampled(ctx, R.indptr, R.indices, R.values, R.indptr_t, R.indices_t, R.values_t,
+                  M0, U, M, DP.n_u, DP.n_m, 50, 0.05, seed=10, n_users=48, n_items=12)
 
 
 def check_sampled(ctx, ip_u, ix_u, va_u, ip_m, ix_m, va_m, M0, U, M, n_u, n_m, n_f, lam, seed,
@@ -120,8 +134,13 @@ def c1():
 
 @pytest.fixture(scope="module")
 def c1_dev(ctx, c1):
+    """Default plans with the benchmark's usual length bins: users with 20..78
+    ratings (67,275 rows) in the dual form; no item has fewer than 79."""
     from paper_1508_03110_amd.solver import DeviceProblem
-    return DeviceProblem(ctx, c1.R, c1.Rt, c1.n_f, c1.lam, torch.float32)
+    DP = DeviceProblem(ctx, c1.R, c1.Rt, c1.n_f, c1.lam, torch.float32)
+    DP.R.set_dual(78)
+    assert DP.R.info()["dual_rows"] == 67275
+    return DP
 
 
 @pytest.mark.timeout(300)
