@@ -124,6 +124,10 @@ int als_ctx_create(als_ctx **out, int device) {
     }
     c->scratch = (double *)sp;
     c->scratch_doubles = alsncg::kScratchDoubles;
+    if (hipMalloc((void **)&c->ybits, 256) != hipSuccess) {
+        delete c;
+        return ALS_E_NOMEM;
+    }
     *out = c;
     return ALS_OK;
 }
@@ -133,6 +137,7 @@ void als_ctx_destroy(als_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->ybits) (void)hipFree(ctx->ybits);
     delete ctx;
 }
 
@@ -527,7 +532,7 @@ int fold_in(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int ld, doubl
     if (n_req == 0) return ALS_OK;
     if (!req_indptr || !req_items || !req_vals || !U_out) return ALS_E_INVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
-    return launch_fold_in(ctx, M, n_f, ld, lambda, dt, n_req, req_indptr, req_items, req_vals,
+    return launch_fold_in(ctx, M, n_items, n_f, ld, lambda, dt, n_req, req_indptr, req_items, req_vals,
                           U_out, req_status, (hipStream_t)stream);
 }
 

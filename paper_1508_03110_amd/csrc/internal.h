@@ -1,5 +1,5 @@
 // Internal declarations shared by the HIP translation units of libalsncg.
-// gfx950 (CDNA4) only: 64-lane wavefronts, MFMA 16x16x4 tiles.
+// gfx950 (CDNA4) only: 64-lane wavefronts, 16x16 MFMA tiles.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -162,6 +162,9 @@ struct Ctx {
     // device (looked up once at creation) and its size in doubles
     double *scratch = nullptr;
     size_t scratch_doubles = 0;
+    // device word for the FP32 half-sweep's scale (bits of max |Y|),
+    // rewritten before every FP32 half-sweep on this context
+    unsigned *ybits = nullptr;
     // Returns workspace of at least `bytes` (grows; synchronises before freeing).
     void *workspace(size_t bytes, hipStream_t stream, int *err);
 };
@@ -183,16 +186,22 @@ int launch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, vo
 int launch_sweep_dual(const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f, int ld,
                       double lambda, als_dtype dt, const void *X_at, void *grad_out,
                       int64_t *bad_row, hipStream_t s);
-int launch_fold_in(Ctx *ctx, const void *M, int n_f, int ld, double lambda, als_dtype dt,
-                   int64_t n_req, const int64_t *indptr, const int32_t *items, const float *vals,
-                   void *U_out, int32_t *status, hipStream_t s);
+int launch_fold_in(Ctx *ctx, const void *M, int64_t n_items, int n_f, int ld, double lambda,
+                   als_dtype dt, int64_t n_req, const int64_t *indptr, const int32_t *items,
+                   const float *vals, void *U_out, int32_t *status, hipStream_t s);
+// *out = bit pattern of max |Y| over the n x n_f block of Y (row stride ld):
+// the scale of the FP32 half-sweep's FP16-split Gram.  Two launches (a
+// fill, then an integer max), stream-ordered, no memset.
+int launch_abs_max_bits(const float *Y, int64_t n, int n_f, int ld, unsigned *out, hipStream_t s);
 // Planned half-sweep over a caller-built plan with caller-provided split-K
 // workspace (sweep_partial_bytes per split chunk) and per-row status (empty
 // row: ALS_E_INVAL, not SPD: ALS_E_NOT_SPD, else 0).  Used by the fold-in
 // server, which builds one plan per batch.
 size_t sweep_partial_bytes(int n_f, als_dtype dt);
-int launch_sweep_batch(const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f, int ld,
-                       double lambda, als_dtype dt, void *partial, int32_t *status, hipStream_t s);
+// ybits: launch_abs_max_bits of Y (FP32; ignored for FP64).
+int launch_sweep_batch(const Plan *plan, const als_csr *R, const void *Y, const unsigned *ybits,
+                       void *X, int n_f, int ld, double lambda, als_dtype dt, void *partial,
+                       int32_t *status, hipStream_t s);
 // Reduced-precision half-sweep (BF16 copies, BF16 MFMA Gram, FP32 solve,
 // optional refinement against the FP32 factors); planned only.
 int launch_sweep_mixed(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y16,

@@ -64,6 +64,9 @@ using namespace alsncg;
 struct als_server {
     Ctx *ctx = nullptr;
     const void *M = nullptr;
+    // bits of max |M| (scale of the FP32 Gram), computed once: M does not
+    // change while the server lives
+    unsigned *ybits = nullptr;
     int64_t n_items = 0;
     int n_f = 0, ld = 0;
     double lambda = 0;
@@ -201,8 +204,8 @@ int launch_batch(als_server *S, Slot &sl, std::vector<Req> &batch) {
     R.values = (const float *)(sl.d_in + o_va);
     const size_t u_bytes = al((size_t)rows * S->ld * S->elt);
     int32_t *d_status = (int32_t *)(sl.d_out + u_bytes);
-    int rc = launch_sweep_batch(&plan, &R, S->M, sl.d_out, S->n_f, S->ld, S->lambda, S->dt,
-                                sl.d_partial, d_status, sl.stream);
+    int rc = launch_sweep_batch(&plan, &R, S->M, S->ybits, sl.d_out, S->n_f, S->ld, S->lambda,
+                                S->dt, sl.d_partial, d_status, sl.stream);
     if (rc != ALS_OK) return rc;
     if (hipMemcpyAsync(sl.h_out, sl.d_out, u_bytes + (size_t)rows * 4, hipMemcpyDeviceToHost,
                        sl.stream) != hipSuccess)
@@ -317,6 +320,8 @@ void free_slots(als_server *S) {
         if (sl.d_partial) (void)hipFree(sl.d_partial);
     }
     S->slots.clear();
+    if (S->ybits) (void)hipFree(S->ybits);
+    S->ybits = nullptr;
 }
 
 }  // namespace
@@ -363,6 +368,19 @@ int als_server_create(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int
     S->cap_chunks = S->cap_rows + S->cap_split;
     S->slots.resize(cfg->max_inflight);
     int rc = ALS_OK;
+    if (dt == ALS_F32) {
+        if (hipMalloc((void **)&S->ybits, 256) != hipSuccess) {
+            delete S;
+            return ALS_E_NOMEM;
+        }
+        rc = launch_abs_max_bits((const float *)M, n_items, n_f, ld, S->ybits, nullptr);
+        if (rc == ALS_OK && hipStreamSynchronize(nullptr) != hipSuccess) rc = ALS_E_HIP;
+        if (rc != ALS_OK) {
+            (void)hipFree(S->ybits);
+            delete S;
+            return rc;
+        }
+    }
     for (auto &sl : S->slots) {
         sl.in_bytes = in_bytes_for(S->cap_rows, S->cap_ratings, S->cap_chunks, S->cap_split);
         sl.out_bytes = al((size_t)S->cap_rows * ld * S->elt) + al((size_t)S->cap_rows * 4);

@@ -119,103 +119,15 @@ __device__ __forceinline__ void finish_operand(T (&gv)[NB], bool ok, T r, int n_
     }
 }
 
-// Tiles (a, b) with b < NBC of the upper triangle (NBC = NB: all of them).
-template <typename T, int NB, int NBC = NB>
+// One MFMA per upper-triangular tile.
+template <typename T, int NB>
 __device__ __forceinline__ void gram_update(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
                                             const T (&gv)[NB]) {
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int bb = a; bb < NBC; ++bb)
+        for (int bb = a; bb < NB; ++bb)
             A[Tri<NB>::id(a, bb)] = Mfma<T>::mma(gv[a], gv[bb], A[Tri<NB>::id(a, bb)]);
-}
-
-// ---------------------------------------------------------------- last block column
-//
-// The last 16-wide block column L = NB - 1 holds only k_L = n_f + 1 - 16 (NB - 1)
-// real slots (5 at n_f = 100, 3 at n_f = 50), but a 16x16x4 tile computes all
-// 16 of its columns.  With LQ > 0 (FP32, k_L <= 4 LQ) that column is built
-// on v_mfma_f32_4x4x1_16b_f32 instead: 16 independent 4x4 blocks per
-// instruction, lane 4b + j holding in register r the product of the A value
-// of lane 4b + r and the B value of lane 4b + j.  Per rating t and half h of
-// the rows, A = y_t[slot 64 h + lane] and B = y_t[slot 16 L + 4 q + lane % 4],
-// so one instruction covers 64 rows x 4 columns of one rating: per group of
-// 4 ratings NH * LQ * 4 such instructions (8 cycles each) replace NB tiles
-// of 32 cycles.  The A operands come from the gathered registers by a 4x4
-// transposition of (lane row, register) with the lane-swap instructions
-// (gv[4 h + k] of row t -> register t of row k); B by one cross-lane
-// permute.  Used for NB = 3 and 4 (one half of rows, see run_sweep).
-template <int NB> struct LCol {
-    static constexpr int NH = (NB + 3) / 4;  // row halves of 64
-};
-
-// In: R[k] = register 4 h + k of every lane row.  Out: R[t] at lane row g
-// = the input R[g] at lane row t (rows are 16 lanes).
-__device__ __forceinline__ void transpose_rows4(float (&R)[4]) {
-    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(R[0]), __float_as_uint(R[2]), false, false);
-    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(R[1]), __float_as_uint(R[3]), false, false);
-    auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
-    auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
-    R[0] = __uint_as_float(c[0]);
-    R[1] = __uint_as_float(c[1]);
-    R[2] = __uint_as_float(d[0]);
-    R[3] = __uint_as_float(d[1]);
-}
-
-template <int NB, int LQ>
-__device__ __forceinline__ void lcol_update(typename Mfma<float>::acc4 (&Dl)[LCol<NB>::NH * LQ],
-                                            const float (&gv)[NB], int lane) {
-    constexpr int NH = LCol<NB>::NH;
-    constexpr int L = NB - 1;
-    float At[NH][4];
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) At[h][k] = (4 * h + k < NB) ? gv[4 * h + k] : 0.0f;
-        transpose_rows4(At[h]);
-    }
-#pragma unroll
-    for (int q = 0; q < LQ; ++q) {
-        // B of rating t: slot 16 L + 4 q + lane % 4 sits in lane row L % 4 of
-        // the transposed half L / 4, lane column 4 q + lane % 4
-        const int src = (16 * (L % 4) + 4 * q + (lane & 3)) << 2;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const float bq = __int_as_float(
-                __builtin_amdgcn_ds_bpermute(src, __float_as_int(At[L / 4][t])));
-#pragma unroll
-            for (int h = 0; h < NH; ++h)
-                Dl[h * LQ + q] = __builtin_amdgcn_mfma_f32_4x4x1f32(At[h][t], bq, Dl[h * LQ + q], 0, 0, 0);
-        }
-    }
-}
-
-// The last block column's tiles (a, L) out of the 4x4 blocks, through LDS
-// (lds: 16 NB x 4 LQ floats); columns past 4 LQ are zero.
-template <int NB, int LQ>
-__device__ __forceinline__ void lcol_to_tiles(typename Mfma<float>::acc4 (&A)[Tri<NB>::NT],
-                                              const typename Mfma<float>::acc4 (&Dl)[LCol<NB>::NH * LQ],
-                                              float *lds, int lane) {
-    constexpr int NH = LCol<NB>::NH;
-    constexpr int W = 4 * LQ;
-    constexpr int L = NB - 1;
-    const int g = lane >> 4, c = lane & 15;
-#pragma unroll
-    for (int h = 0; h < NH; ++h)
-#pragma unroll
-        for (int q = 0; q < LQ; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 64 * h + 4 * (lane >> 2) + r;
-                if (row < 16 * NB) lds[row * W + 4 * q + (lane & 3)] = Dl[h * LQ + q][r];
-            }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            A[Tri<NB>::id(a, L)][r] = c < W ? lds[(16 * a + Mfma<float>::row(g, r)) * W + c] : 0.0f;
-    __syncthreads();
 }
 
 // Gram accumulation over ratings [b, e) of one row.  kGramDepth register
@@ -237,9 +149,8 @@ __device__ __forceinline__ void lcol_to_tiles(typename Mfma<float>::acc4 (&A)[Tr
 // Loads for groups past the end read valid addresses and are discarded.
 constexpr int kGramDepth = 3;
 
-template <typename T, int NB, bool VEC, int LQ = 0>
+template <typename T, int NB, bool VEC>
 __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<NB>::NT],
-                                                typename Mfma<T>::acc4 (&Dl)[LCol<NB>::NH * (LQ ? LQ : 1)],
                                                 const int32_t *__restrict__ idx,
                                                 const float *__restrict__ val, int64_t b, int64_t e,
                                                 const T *__restrict__ Y, int ld, int n_f, int g,
@@ -279,15 +190,207 @@ __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<
             rq[slot] = vx[p];
             if (s + k < ng) {
                 finish_operand<T, NB>(buf[k], 4 * (s + k) + g <= last, (T)rv[k], n_f, c);
-                if constexpr (LQ > 0) {
-                    gram_update<T, NB, NB - 1>(A, buf[k]);
-                    lcol_update<NB, LQ>(Dl, buf[k], 16 * g + c);
-                } else {
-                    gram_update<T, NB>(A, buf[k]);
-                }
+                gram_update<T, NB>(A, buf[k]);
             }
         }
     }
+}
+
+// ---------------------------------------------------------------- FP32 Gram on FP16 MFMAs
+//
+// The FP32 half-sweep accumulates its Gram tiles from two-term FP16 splits
+// of the gathered rows on v_mfma_f32_16x16x32_f16 (32 ratings per
+// instruction, about 16 cycles; the same 32 ratings take 8 x 32 cycles of
+// v_mfma_f32_16x16x4f32).  With x = 2^s y (s per chunk, so that every
+// |x| < 2^14: the FP16 range holds x and its low part stays normal for
+// all |x| above 2^-3 of the largest), x = h + m + d where h = fp16(x) and
+// m = fp16(x - h), both rounded to nearest: x - h is exact in FP32 and
+// |d| <= 2^-22 |x|.  Then
+//     x_a x_b ~ h_a h_b + h_a m_b + m_a h_b
+// drops m_a m_b (at most 2^-22 |x_a x_b|, unbiased off the diagonal since
+// m has either sign); the three products are exact in FP32 and the MFMA
+// adds them into FP32 accumulators.  The tiles are scaled back by 2^-2s
+// (exact) at the end, so per rating the Gram carries about the error of
+// FP32 rounding.
+//
+// Lanes: l = 16 g + c.  For a group of 32 ratings lane group g owns
+// ratings 8 g .. 8 g + 7 and lane c slot 16 a + c of every block a; the
+// operand of block a is the 8 FP16 values of those ratings at that slot,
+// which is the A[c][8g..8g+7] (and B[8g..8g+7][c]) operand layout of the
+// 16x16x32 MFMA.  The slots are those of Slots<NB> (same loads as the
+// 16x16x4 path, 8 rows per lane instead of 1), and the rating rides in
+// slot n_f: lane c = n_f - 16 (NB - 1) loads it in place of a factor
+// element, so no separate value register is kept per rating.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ Mfma<float>::acc4 mma_f16(u32x4_t a, u32x4_t b, Mfma<float>::acc4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a),
+                                                  __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
+}
+
+// Two scaled values -> packed FP16 high parts and packed FP16 low parts.
+__device__ __forceinline__ void split2(float x0, float x1, unsigned &hi, unsigned &lo) {
+    const float2_t x = {x0, x1};
+    const half2_t h = __builtin_convertvector(x, half2_t);
+    const half2_t m = __builtin_convertvector(x - __builtin_convertvector(h, float2_t), half2_t);
+    hi = __builtin_bit_cast(unsigned, h);
+    lo = __builtin_bit_cast(unsigned, m);
+}
+
+// s with 2^s M < 2^14 for M = max(max |Y|, max |r|) given as the bits of two
+// non-negative floats; clamped to [-60, 60] so that 2^s and 2^-2s are normal
+// FP32 numbers (a Gram of entries above 2^74 overflows FP32 anyway).
+// Non-finite or zero M: s = 0.
+__device__ __forceinline__ int split_shift(unsigned ybits, unsigned rbits) {
+    const unsigned mb = max(ybits, rbits);
+    if (mb == 0u || mb >= 0x7f800000u) return 0;
+    const int e = (int)(mb >> 23) - 126;  // M < 2^e
+    return min(max(14 - e, -60), 60);
+}
+
+// Largest |r| over the ratings vx[p0 .. p0 + 16 kWave - 1] (clamped at
+// last) seen by this lane: 16 loads in flight.
+__device__ __forceinline__ float abs_max_step(const float *__restrict__ vx, int p0, int last,
+                                              int lane) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = vx[min(p0 + kWave * u + lane, last)];
+    float m = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) m = fmaxf(m, fabsf(v[u]));
+    return m;
+}
+
+__device__ __forceinline__ float wave_max(float m) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+    return m;
+}
+
+// One factor row (slot order of Slots<NB>) for lane c; in the last block the
+// lane of slot n_f reads the rating at rp instead.  Loads are unconditional
+// (clamped columns; the masks are applied when the operands are built).
+template <int NB, bool VEC>
+__device__ __forceinline__ void gather_aug(float (&gv)[NB], const float *__restrict__ Y, int j,
+                                           int ld, int n_f, int c, const float *rp) {
+    typedef Slots<NB> SL;
+    static_assert(4 * SL::Q + 2 * SL::P < NB, "the last block is loaded per element");
+    const float *row = Y + (int64_t)j * ld;
+#pragma unroll
+    for (int q = 0; q < SL::Q; ++q) {
+        const float *p4 = row + 64 * q + 4 * c;
+        if constexpr (VEC) {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 v = *(const f4 *)p4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) gv[4 * q + e] = v[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) gv[4 * q + e] = p4[e];
+        }
+    }
+    if constexpr (SL::P == 1) {
+        const float *p2 = row + 64 * SL::Q + 2 * c;
+        if constexpr (VEC) {
+            const float2_t v = *(const float2_t *)p2;
+            gv[4 * SL::Q] = v[0];
+            gv[4 * SL::Q + 1] = v[1];
+        } else {
+            gv[4 * SL::Q] = p2[0];
+            gv[4 * SL::Q + 1] = p2[1];
+        }
+    }
+#pragma unroll
+    for (int cb = 4 * SL::Q + 2 * SL::P; cb < NB - 1; ++cb) gv[cb] = row[cb * 16 + c];
+    const int col = (NB - 1) * 16 + c;
+    gv[NB - 1] = *(col == n_f ? rp : row + min(col, n_f - 1));
+}
+
+// Gram of ratings [b, e) into A (FP32 tiles, unscaled).  One register
+// buffer of gathered rows: group t is split into its FP16 operands first,
+// which frees the buffer, then the rows of group t + 1 are gathered into it
+// and stay in flight while group t's MFMAs run; the ids of group t + 2 are
+// loaded after that gather, so waiting for them later never waits for a
+// gather issued after them (the wait counter completes loads in issue
+// order).  Scheduling barriers keep the three phases in this order (left to
+// itself the scheduler sinks the gathers among the MFMAs, and the
+// registers of two groups then spill).  Loads past the end of the chunk
+// read clamped (valid) positions and are zeroed by the scale.
+template <int NB, bool VEC>
+__device__ __forceinline__ void gram_split(Mfma<float>::acc4 (&A)[Tri<NB>::NT],
+                                           const int32_t *__restrict__ idx,
+                                           const float *__restrict__ val, int64_t b, int64_t e,
+                                           const float *__restrict__ Y, int ld, int n_f,
+                                           unsigned ybits, int g, int c) {
+    typedef Tri<NB> TR;
+    if (b >= e) return;
+    const int last = (int)(e - 1 - b);
+    const int ng = (last >> 5) + 1;
+    const int32_t *ix = idx + b;
+    const float *vx = val + b;
+    auto pos = [&](int t, int k) { return min(32 * t + 8 * g + k, last); };
+    float buf[8][NB];
+    int jq[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) jq[k] = ix[pos(0, k)];
+    // the scale needs the largest rating of the chunk: its first loads go
+    // out before the first gather, so waiting for them leaves the gather in
+    // flight
+    float rmax = abs_max_step(vx, 0, last, 16 * g + c);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        gather_aug<NB, VEC>(buf[k], Y, jq[k], ld, n_f, c, vx + pos(0, k));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) jq[k] = ix[pos(1, k)];
+    for (int p0 = 16 * kWave; p0 <= last; p0 += 16 * kWave)
+        rmax = fmaxf(rmax, abs_max_step(vx, p0, last, 16 * g + c));
+    const int sh = split_shift(ybits, __float_as_uint(wave_max(rmax)));
+    const float S = __int_as_float((127 + sh) << 23);
+    const bool lane_real = c <= n_f - 16 * (NB - 1);  // last block: real slot or the rating
+    for (int t = 0; t < ng; ++t) {
+        const int rem = last - (32 * t + 8 * g);  // ratings k <= rem are real
+        u32x4_t hp[NB], lp[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float s0 = 2 * i <= rem ? S : 0.0f, s1 = 2 * i + 1 <= rem ? S : 0.0f;
+                if (a == NB - 1) {
+                    s0 = lane_real ? s0 : 0.0f;
+                    s1 = lane_real ? s1 : 0.0f;
+                }
+                unsigned hi, lo;
+                split2(buf[2 * i][a] * s0, buf[2 * i + 1][a] * s1, hi, lo);
+                hp[a][i] = hi;
+                lp[a][i] = lo;
+            }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            gather_aug<NB, VEC>(buf[k], Y, jq[k], ld, n_f, c, vx + pos(t + 1, k));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb) A[TR::id(a, bb)] = mma_f16(hp[a], hp[bb], A[TR::id(a, bb)]);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb) A[TR::id(a, bb)] = mma_f16(hp[a], lp[bb], A[TR::id(a, bb)]);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb) A[TR::id(a, bb)] = mma_f16(lp[a], hp[bb], A[TR::id(a, bb)]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) jq[k] = ix[pos(t + 2, k)];
+    }
+    const float U = __int_as_float((127 - 2 * sh) << 23);
+#pragma unroll
+    for (int t = 0; t < TR::NT; ++t) A[t] *= U;
 }
 
 // Regularise, optionally form the gradient 2 (A x_in - v), factorise, solve
@@ -399,10 +502,11 @@ template <typename T, int NB> struct Occ {
 
 // One chunk: Gram of its ratings, then either the partial tiles (split row)
 // or the row solve.
-template <typename T, int NB, bool VEC, int LQ>
+template <typename T, int NB, bool VEC>
 __device__ __forceinline__ void sweep_chunk(
     int64_t q, const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
-    const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
+    const float *__restrict__ val, const T *__restrict__ Y, const unsigned *__restrict__ ybits,
+    T *__restrict__ X, int n_f, int ld,
     T lambda, const int32_t *__restrict__ chunk_row, const int64_t *__restrict__ chunk_begin,
     const int32_t *__restrict__ chunk_len, const int32_t *__restrict__ chunk_slot,
     typename Mfma<T>::acc4 *__restrict__ partial, const T *__restrict__ X_at,
@@ -427,11 +531,10 @@ __device__ __forceinline__ void sweep_chunk(
     acc4 A[TR::NT];
 #pragma unroll
     for (int t = 0; t < TR::NT; ++t) A[t] = acc4{T(0), T(0), T(0), T(0)};
-    acc4 Dl[LCol<NB>::NH * (LQ ? LQ : 1)];
-#pragma unroll
-    for (int t = 0; t < LCol<NB>::NH * (LQ ? LQ : 1); ++t) Dl[t] = acc4{T(0), T(0), T(0), T(0)};
-    gram_accumulate<T, NB, VEC, LQ>(A, Dl, idx, val, b, b + len, Y, ld, n_f, g, c);
-    if constexpr (LQ > 0) lcol_to_tiles<NB, LQ>(A, Dl, sm, lane);
+    if constexpr (sizeof(T) == 4)
+        gram_split<NB, VEC>(A, idx, val, b, b + len, Y, ld, n_f, *ybits, g, c);
+    else
+        gram_accumulate<T, NB, VEC>(A, idx, val, b, b + len, Y, ld, n_f, g, c);
     if (slot >= 0) {
         acc4 *dst = partial + (int64_t)slot * TR::NT * kWave;
 #pragma unroll
@@ -447,10 +550,11 @@ __device__ __forceinline__ void sweep_chunk(
 // striding over the chunks (PERSIST = true; chunks are ordered longest
 // first, so the stride deals them out like a greedy schedule).
 // chunk_row == nullptr: chunk q is row q in full (fold-in and unplanned use).
-template <typename T, int NB, bool PERSIST, bool VEC, int LQ = 0>
+template <typename T, int NB, bool PERSIST, bool VEC>
 __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
-    const float *__restrict__ val, const T *__restrict__ Y, T *__restrict__ X, int n_f, int ld,
+    const float *__restrict__ val, const T *__restrict__ Y, const unsigned *__restrict__ ybits,
+    T *__restrict__ X, int n_f, int ld,
     T lambda, int64_t n_chunks, const int32_t *__restrict__ chunk_row,
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ chunk_slot, typename Mfma<T>::acc4 *__restrict__ partial,
@@ -459,13 +563,13 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     __shared__ T sm[Shared<T, NB>::size];
     if constexpr (PERSIST) {
         for (int64_t q = blockIdx.x; q < n_chunks; q += gridDim.x)
-            sweep_chunk<T, NB, VEC, LQ>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row,
+            sweep_chunk<T, NB, VEC>(q, indptr, idx, val, Y, ybits, X, n_f, ld, lambda, chunk_row,
                                     chunk_begin, chunk_len, chunk_slot, partial, X_at, grad_out,
                                     bad_row, status, empty_status, sm);
     } else {
         const int64_t q = blockIdx.x;
         if (q >= n_chunks) return;
-        sweep_chunk<T, NB, VEC, LQ>(q, indptr, idx, val, Y, X, n_f, ld, lambda, chunk_row,
+        sweep_chunk<T, NB, VEC>(q, indptr, idx, val, Y, ybits, X, n_f, ld, lambda, chunk_row,
                                 chunk_begin, chunk_len, chunk_slot, partial, X_at, grad_out,
                                 bad_row, status, empty_status, sm);
     }
@@ -502,20 +606,65 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_split_kernel(
 }
 
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
+__global__ void set_u32_kernel(unsigned *p, unsigned v) { *p = v; }
 
-template <typename T, int NB, bool VEC, int LQ = 0>
-int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
-              T lambda, const T *X_at, T *grad_out, int64_t *bad_row, int32_t *status, int empty_status,
-              int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
+// *out = max(*out, bit pattern of max |Y|) over the n x n_f block of Y (row
+// stride ld): the integer order of the bit patterns of non-negative floats
+// is their numeric order (NaN above infinity), so the maximum is exact and
+// independent of the schedule.  A wavefront takes 8 rows per step, lanes
+// over the columns (n_f <= 192); loads are clamped into the block.
+constexpr int kAbsMaxRows = 8;
+__global__ __launch_bounds__(256) void abs_max_bits_kernel(const float *__restrict__ Y, int64_t n,
+                                                           int n_f, int ld, unsigned *out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned m = 0u;
+    for (int64_t r0 = w0 * kAbsMaxRows; r0 < n; r0 += nw * kAbsMaxRows) {
+        unsigned v[kAbsMaxRows][3];
+#pragma unroll
+        for (int u = 0; u < kAbsMaxRows; ++u)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int64_t r = min(r0 + u, n - 1);
+                const int col = min(lane + kWave * q, n_f - 1);
+                v[u][q] = __float_as_uint(Y[r * ld + col]) & 0x7fffffffu;
+            }
+#pragma unroll
+        for (int u = 0; u < kAbsMaxRows; ++u)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) m = max(m, v[u][q]);
+    }
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
+    if (lane == 0) atomicMax(out, m);
+}
+
+// FP32: ybits holds the bits of max |Y| (abs_max_bits_kernel); null: it is
+// computed here into the context's word first (over the R->n_cols rows of Y).
+template <typename T, int NB, bool VEC>
+int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, const unsigned *ybits,
+                T *X, int n_f, int ld, T lambda, const T *X_at, T *grad_out, int64_t *bad_row,
+                int32_t *status, int empty_status, int64_t n_rows_unplanned, void *partial_ext,
+                hipStream_t s) {
     typedef typename Mfma<T>::acc4 acc4;
     typedef Tri<NB> TR;
+    if constexpr (sizeof(T) == 4) {
+        if (!ybits) {
+            if (!ctx || !ctx->ybits) return ALS_E_INVAL;
+            const int rc = launch_abs_max_bits((const float *)Y, R->n_cols, n_f, ld, ctx->ybits, s);
+            if (rc != ALS_OK) return rc;
+            ybits = ctx->ybits;
+        }
+    }
     if (bad_row) hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, s, bad_row, (int64_t)LLONG_MAX);
     if (!plan) {
         if (n_rows_unplanned > 0)
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC, LQ>), dim3((unsigned)n_rows_unplanned),
-                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
-                               lambda, n_rows_unplanned, nullptr, nullptr, nullptr, nullptr,
-                               (acc4 *)nullptr, X_at, grad_out, bad_row, status, empty_status);
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)n_rows_unplanned),
+                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, ybits, X,
+                               n_f, ld, lambda, n_rows_unplanned, nullptr, nullptr, nullptr,
+                               nullptr, (acc4 *)nullptr, X_at, grad_out, bad_row, status,
+                               empty_status);
         return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
     }
     acc4 *partial = (acc4 *)partial_ext;
@@ -530,16 +679,16 @@ int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, 
     const int64_t n_main = dual ? plan->n_chunks - plan->n_dual : plan->n_chunks;
     if (n_main > 0) {
         if (plan->grid > 0)
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true, VEC, LQ>),
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true, VEC>),
                                dim3((unsigned)std::min<int64_t>(plan->grid, n_main)),
-                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
-                               lambda, n_main, plan->chunk_row, plan->chunk_begin,
+                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, ybits, X,
+                               n_f, ld, lambda, n_main, plan->chunk_row, plan->chunk_begin,
                                plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
                                status, empty_status);
         else
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC, LQ>), dim3((unsigned)n_main),
-                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, X, n_f, ld,
-                               lambda, n_main, plan->chunk_row, plan->chunk_begin,
+            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)n_main),
+                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, ybits, X,
+                               n_f, ld, lambda, n_main, plan->chunk_row, plan->chunk_begin,
                                plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
                                status, empty_status);
     }
@@ -557,52 +706,32 @@ int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, 
 }
 
 template <typename T, int NB>
-int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld,
-              T lambda, const T *X_at, T *grad_out, int64_t *bad_row, int32_t *status, int empty_status,
-              int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
-    if constexpr (sizeof(T) == 4 && (NB == 3 || NB == 4)) {
-        // the last block column on 4x4 MFMA blocks when its rows fit one
-        // half of 64 and it holds at most 4 real slots (NB = 3) or 8
-        // (NB = 4): measured, e.g. both half-sweeps at n_f = 50 take 20-25 %
-        // less time; with two halves (NB = 7, n_f = 100) the transpositions
-        // and permutes cost more than the MFMA cycles saved
-        const int kl = n_f + 1 - 16 * (NB - 1);
-        const bool vec = ld % 4 == 0 && ((uintptr_t)Y % 16) == 0;
-#define ALS_SWEEP_LQ(V, Q)                                                                          \
-    return run_sweep_v<T, NB, V, Q>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out, bad_row, \
-                                    status, empty_status, n_rows_unplanned, partial_ext, s)
-        if (kl <= 4) {
-            if (vec) ALS_SWEEP_LQ(true, 1);
-            ALS_SWEEP_LQ(false, 1);
-        }
-        if constexpr (NB == 4) {
-            if (kl <= 8) {
-                if (vec) ALS_SWEEP_LQ(true, 2);
-                ALS_SWEEP_LQ(false, 2);
-            }
-        }
-#undef ALS_SWEEP_LQ
-    }
+int run_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, const unsigned *ybits,
+              T *X, int n_f, int ld, T lambda, const T *X_at, T *grad_out, int64_t *bad_row,
+              int32_t *status, int empty_status, int64_t n_rows_unplanned, void *partial_ext,
+              hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
         if (ld % 4 == 0 && ((uintptr_t)Y % 16) == 0)
-            return run_sweep_v<T, NB, true>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out,
-                                            bad_row, status, empty_status, n_rows_unplanned,
-                                            partial_ext, s);
+            return run_sweep_v<T, NB, true>(ctx, plan, R, Y, ybits, X, n_f, ld, lambda, X_at,
+                                            grad_out, bad_row, status, empty_status,
+                                            n_rows_unplanned, partial_ext, s);
     }
-    return run_sweep_v<T, NB, false>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out, bad_row,
-                                     status, empty_status, n_rows_unplanned, partial_ext, s);
+    return run_sweep_v<T, NB, false>(ctx, plan, R, Y, ybits, X, n_f, ld, lambda, X_at, grad_out,
+                                     bad_row, status, empty_status, n_rows_unplanned, partial_ext,
+                                     s);
 }
 
 template <typename T>
-int dispatch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f,
-                   int ld, double lambda, const void *X_at, void *grad_out, int64_t *bad_row, int32_t *status,
+int dispatch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y,
+                   const unsigned *ybits, void *X, int n_f, int ld, double lambda,
+                   const void *X_at, void *grad_out, int64_t *bad_row, int32_t *status,
                    int empty_status, int64_t n_rows_unplanned, void *partial_ext, hipStream_t s) {
     const int nb = (n_f + 1 + 15) / 16;
 #define ALS_SWEEP_CASE(NBV)                                                                      \
     case NBV:                                                                                    \
-        return run_sweep<T, NBV>(ctx, plan, R, (const T *)Y, (T *)X, n_f, ld, (T)lambda,         \
-                                 (const T *)X_at, (T *)grad_out, bad_row, status, empty_status, n_rows_unplanned, \
-                                 partial_ext, s);
+        return run_sweep<T, NBV>(ctx, plan, R, (const T *)Y, ybits, (T *)X, n_f, ld, (T)lambda,  \
+                                 (const T *)X_at, (T *)grad_out, bad_row, status, empty_status,  \
+                                 n_rows_unplanned, partial_ext, s);
     if constexpr (sizeof(T) == 4) {
         switch (nb) {
             ALS_SWEEP_CASE(1)
@@ -632,34 +761,45 @@ int dispatch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, 
 
 }  // namespace
 
+int launch_abs_max_bits(const float *Y, int64_t n, int n_f, int ld, unsigned *out, hipStream_t s) {
+    hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(1), 0, s, out, 0u);
+    if (Y && n > 0 && n_f > 0) {
+        const int64_t per_block = 4 * kAbsMaxRows;
+        const unsigned blocks = (unsigned)std::min<int64_t>((n + per_block - 1) / per_block, 8192);
+        hipLaunchKernelGGL(abs_max_bits_kernel, dim3(blocks), dim3(256), 0, s, Y, n, n_f, ld, out);
+    }
+    return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
+}
+
 int launch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f,
                  int ld, double lambda, als_dtype dt, const void *X_at, void *grad_out,
                  int64_t *bad_row, hipStream_t s) {
     if (dt == ALS_F32)
-        return dispatch_sweep<float>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out, bad_row,
-                                     nullptr, 0, 0, nullptr, s);
+        return dispatch_sweep<float>(ctx, plan, R, Y, nullptr, X, n_f, ld, lambda, X_at, grad_out,
+                                     bad_row, nullptr, 0, 0, nullptr, s);
     if (dt == ALS_F64)
-        return dispatch_sweep<double>(ctx, plan, R, Y, X, n_f, ld, lambda, X_at, grad_out,
-                                      bad_row, nullptr, 0, 0, nullptr, s);
+        return dispatch_sweep<double>(ctx, plan, R, Y, nullptr, X, n_f, ld, lambda, X_at,
+                                      grad_out, bad_row, nullptr, 0, 0, nullptr, s);
     return ALS_E_INVAL;
 }
 
-int launch_fold_in(Ctx *ctx, const void *M, int n_f, int ld, double lambda, als_dtype dt,
-                   int64_t n_req, const int64_t *indptr, const int32_t *items, const float *vals,
-                   void *U_out, int32_t *status, hipStream_t s) {
+int launch_fold_in(Ctx *ctx, const void *M, int64_t n_items, int n_f, int ld, double lambda,
+                   als_dtype dt, int64_t n_req, const int64_t *indptr, const int32_t *items,
+                   const float *vals, void *U_out, int32_t *status, hipStream_t s) {
     als_csr R;
     R.n_rows = n_req;
-    R.n_cols = 0;
+    R.n_cols = n_items;
     R.nnz = 0;
     R.indptr = indptr;
     R.indices = items;
     R.values = vals;
     if (dt == ALS_F32)
-        return dispatch_sweep<float>(ctx, nullptr, &R, M, U_out, n_f, ld, lambda, nullptr, nullptr,
-                                     nullptr, status, ALS_E_INVAL, n_req, nullptr, s);
+        return dispatch_sweep<float>(ctx, nullptr, &R, M, nullptr, U_out, n_f, ld, lambda, nullptr,
+                                     nullptr, nullptr, status, ALS_E_INVAL, n_req, nullptr, s);
     if (dt == ALS_F64)
-        return dispatch_sweep<double>(ctx, nullptr, &R, M, U_out, n_f, ld, lambda, nullptr,
-                                      nullptr, nullptr, status, ALS_E_INVAL, n_req, nullptr, s);
+        return dispatch_sweep<double>(ctx, nullptr, &R, M, nullptr, U_out, n_f, ld, lambda,
+                                      nullptr, nullptr, nullptr, status, ALS_E_INVAL, n_req,
+                                      nullptr, s);
     return ALS_E_INVAL;
 }
 
@@ -669,15 +809,17 @@ size_t sweep_partial_bytes(int n_f, als_dtype dt) {
     return nt * kWave * 4 * (dt == ALS_F64 ? sizeof(double) : sizeof(float));
 }
 
-int launch_sweep_batch(const Plan *plan, const als_csr *R, const void *Y, void *X, int n_f, int ld,
-                       double lambda, als_dtype dt, void *partial, int32_t *status,
-                       hipStream_t s) {
-    if (dt == ALS_F32)
-        return dispatch_sweep<float>(nullptr, plan, R, Y, X, n_f, ld, lambda, nullptr, nullptr,
-                                     nullptr, status, ALS_E_INVAL, 0, partial, s);
+int launch_sweep_batch(const Plan *plan, const als_csr *R, const void *Y, const unsigned *ybits,
+                       void *X, int n_f, int ld, double lambda, als_dtype dt, void *partial,
+                       int32_t *status, hipStream_t s) {
+    if (dt == ALS_F32) {
+        if (!ybits) return ALS_E_INVAL;
+        return dispatch_sweep<float>(nullptr, plan, R, Y, ybits, X, n_f, ld, lambda, nullptr,
+                                     nullptr, nullptr, status, ALS_E_INVAL, 0, partial, s);
+    }
     if (dt == ALS_F64)
-        return dispatch_sweep<double>(nullptr, plan, R, Y, X, n_f, ld, lambda, nullptr, nullptr,
-                                      nullptr, status, ALS_E_INVAL, 0, partial, s);
+        return dispatch_sweep<double>(nullptr, plan, R, Y, nullptr, X, n_f, ld, lambda, nullptr,
+                                      nullptr, nullptr, status, ALS_E_INVAL, 0, partial, s);
     return ALS_E_INVAL;
 }
 
