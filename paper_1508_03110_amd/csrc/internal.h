@@ -114,6 +114,55 @@ template <> __device__ inline float sum4g<float>(float v) {
     return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 template <typename T> __device__ inline T sum64(T v) { return sum4g(sum16(v)); }
+// Maximum over the wavefront (result in every lane).
+__device__ inline float wave_max(float m) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+    return m;
+}
+
+// ---------------------------------------------------------------- FP16-split products
+//
+// FP32 products on FP16 MFMAs: a value x (already scaled by a power of two
+// into the FP16 range) is split into h = fp16(x) and m = fp16(x - h), both
+// rounded to nearest (x - h is exact in FP32, so x = h + m + d with
+// |d| <= 2^-22 |x|), and x_a x_b is taken as h_a h_b + h_a m_b + m_a h_b,
+// three exact FP16 products accumulated in FP32 by
+// v_mfma_f32_16x16x32_f16 (lane l = 16 g + c supplies A[c][8g..8g+7] and
+// B[8g..8g+7][c]; the accumulator layout is that of Mfma<float>).
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ Mfma<float>::acc4 mma_f16(u32x4_t a, u32x4_t b, Mfma<float>::acc4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a),
+                                                  __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
+}
+
+// Two scaled values -> packed FP16 high parts and packed FP16 low parts.
+__device__ __forceinline__ void split2(float x0, float x1, unsigned &hi, unsigned &lo) {
+    const float2_t x = {x0, x1};
+    const half2_t h = __builtin_convertvector(x, half2_t);
+    const half2_t m = __builtin_convertvector(x - __builtin_convertvector(h, float2_t), half2_t);
+    hi = __builtin_bit_cast(unsigned, h);
+    lo = __builtin_bit_cast(unsigned, m);
+}
+
+// 2^e as an FP32 number, -126 <= e <= 127.
+__device__ __forceinline__ float exp2i(int e) { return __int_as_float((127 + e) << 23); }
+
+// s with 2^s M < 2^14 for M = max(a, b) given as the bits of two
+// non-negative floats; clamped to [-60, 60] so that 2^s and 2^-2s are normal
+// FP32 numbers (a Gram of entries above 2^74 overflows FP32 anyway).
+// Non-finite or zero M: s = 0.
+__device__ __forceinline__ int split_shift(unsigned ybits, unsigned rbits) {
+    const unsigned mb = max(ybits, rbits);
+    if (mb == 0u || mb >= 0x7f800000u) return 0;
+    const int e = (int)(mb >> 23) - 126;  // M < 2^e
+    return min(max(14 - e, -60), 60);
+}
+
 
 // ---------------------------------------------------------------- host objects
 

@@ -201,17 +201,18 @@ __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<
 // The FP32 half-sweep accumulates its Gram tiles from two-term FP16 splits
 // of the gathered rows on v_mfma_f32_16x16x32_f16 (32 ratings per
 // instruction, about 16 cycles; the same 32 ratings take 8 x 32 cycles of
-// v_mfma_f32_16x16x4f32).  With x = 2^s y (s per chunk, so that every
-// |x| < 2^14: the FP16 range holds x and its low part stays normal for
-// all |x| above 2^-3 of the largest), x = h + m + d where h = fp16(x) and
+// v_mfma_f32_16x16x4f32).  With x = 2^s y (s = sy for the factor slots from
+// max |Y|, s = sr for the rating slot from the chunk's largest rating, so
+// that every |x| < 2^14: the FP16 range holds x and its low part stays
+// normal for every |x| above 2^-17 of the largest), x = h + m + d where h = fp16(x) and
 // m = fp16(x - h), both rounded to nearest: x - h is exact in FP32 and
 // |d| <= 2^-22 |x|.  Then
 //     x_a x_b ~ h_a h_b + h_a m_b + m_a h_b
 // drops m_a m_b (at most 2^-22 |x_a x_b|, unbiased off the diagonal since
 // m has either sign); the three products are exact in FP32 and the MFMA
-// adds them into FP32 accumulators.  The tiles are scaled back by 2^-2s
-// (exact) at the end, so per rating the Gram carries about the error of
-// FP32 rounding.
+// adds them into FP32 accumulators.  The tiles are scaled back by the
+// exact powers of two at the end, so per rating the Gram carries about the
+// error of FP32 rounding.
 //
 // Lanes: l = 16 g + c.  For a group of 32 ratings lane group g owns
 // ratings 8 g .. 8 g + 7 and lane c slot 16 a + c of every block a; the
@@ -221,36 +222,6 @@ __device__ __forceinline__ void gram_accumulate(typename Mfma<T>::acc4 (&A)[Tri<
 // 16x16x4 path, 8 rows per lane instead of 1), and the rating rides in
 // slot n_f: lane c = n_f - 16 (NB - 1) loads it in place of a factor
 // element, so no separate value register is kept per rating.
-typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-typedef float float2_t __attribute__((ext_vector_type(2)));
-typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ Mfma<float>::acc4 mma_f16(u32x4_t a, u32x4_t b, Mfma<float>::acc4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a),
-                                                  __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
-}
-
-// Two scaled values -> packed FP16 high parts and packed FP16 low parts.
-__device__ __forceinline__ void split2(float x0, float x1, unsigned &hi, unsigned &lo) {
-    const float2_t x = {x0, x1};
-    const half2_t h = __builtin_convertvector(x, half2_t);
-    const half2_t m = __builtin_convertvector(x - __builtin_convertvector(h, float2_t), half2_t);
-    hi = __builtin_bit_cast(unsigned, h);
-    lo = __builtin_bit_cast(unsigned, m);
-}
-
-// s with 2^s M < 2^14 for M = max(max |Y|, max |r|) given as the bits of two
-// non-negative floats; clamped to [-60, 60] so that 2^s and 2^-2s are normal
-// FP32 numbers (a Gram of entries above 2^74 overflows FP32 anyway).
-// Non-finite or zero M: s = 0.
-__device__ __forceinline__ int split_shift(unsigned ybits, unsigned rbits) {
-    const unsigned mb = max(ybits, rbits);
-    if (mb == 0u || mb >= 0x7f800000u) return 0;
-    const int e = (int)(mb >> 23) - 126;  // M < 2^e
-    return min(max(14 - e, -60), 60);
-}
-
 // Largest |r| over the ratings vx[p0 .. p0 + 16 kWave - 1] (clamped at
 // last) seen by this lane: 16 loads in flight.
 __device__ __forceinline__ float abs_max_step(const float *__restrict__ vx, int p0, int last,
@@ -261,12 +232,6 @@ __device__ __forceinline__ float abs_max_step(const float *__restrict__ vx, int 
     float m = 0.0f;
 #pragma unroll
     for (int u = 0; u < 16; ++u) m = fmaxf(m, fabsf(v[u]));
-    return m;
-}
-
-__device__ __forceinline__ float wave_max(float m) {
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
     return m;
 }
 
@@ -347,9 +312,14 @@ __device__ __forceinline__ void gram_split(Mfma<float>::acc4 (&A)[Tri<NB>::NT],
     for (int k = 0; k < 8; ++k) jq[k] = ix[pos(1, k)];
     for (int p0 = 16 * kWave; p0 <= last; p0 += 16 * kWave)
         rmax = fmaxf(rmax, abs_max_step(vx, p0, last, 16 * g + c));
-    const int sh = split_shift(ybits, __float_as_uint(wave_max(rmax)));
-    const float S = __int_as_float((127 + sh) << 23);
-    const bool lane_real = c <= n_f - 16 * (NB - 1);  // last block: real slot or the rating
+    // factor slots scale by 2^sy (max |Y|), the rating slot by 2^sr (the
+    // chunk's largest rating), so that neither magnitude costs the other
+    // its low parts; padding slots by 0
+    const int sy = split_shift(ybits, 0u);
+    const int sr = split_shift(0u, __float_as_uint(wave_max(rmax)));
+    const int caug = n_f - 16 * (NB - 1);  // lane of slot n_f in the last block
+    const float Sy = exp2i(sy);
+    const float Sl = c < caug ? Sy : c == caug ? exp2i(sr) : 0.0f;
     for (int t = 0; t < ng; ++t) {
         const int rem = last - (32 * t + 8 * g);  // ratings k <= rem are real
         u32x4_t hp[NB], lp[NB];
@@ -357,11 +327,8 @@ __device__ __forceinline__ void gram_split(Mfma<float>::acc4 (&A)[Tri<NB>::NT],
         for (int a = 0; a < NB; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float s0 = 2 * i <= rem ? S : 0.0f, s1 = 2 * i + 1 <= rem ? S : 0.0f;
-                if (a == NB - 1) {
-                    s0 = lane_real ? s0 : 0.0f;
-                    s1 = lane_real ? s1 : 0.0f;
-                }
+                const float sa = a == NB - 1 ? Sl : Sy;
+                const float s0 = 2 * i <= rem ? sa : 0.0f, s1 = 2 * i + 1 <= rem ? sa : 0.0f;
                 unsigned hi, lo;
                 split2(buf[2 * i][a] * s0, buf[2 * i + 1][a] * s1, hi, lo);
                 hp[a][i] = hi;
@@ -388,9 +355,23 @@ __device__ __forceinline__ void gram_split(Mfma<float>::acc4 (&A)[Tri<NB>::NT],
 #pragma unroll
         for (int k = 0; k < 8; ++k) jq[k] = ix[pos(t + 2, k)];
     }
-    const float U = __int_as_float((127 - 2 * sh) << 23);
+    // scale back: 2^-2sy (factor x factor), 2^-(sy+sr) (factor x rating),
+    // 2^-2sr (rating x rating); the rating is row and column n_f
+    const float Fyy = exp2i(-2 * sy), Fyr = exp2i(-sy - sr), Frr = exp2i(-2 * sr);
 #pragma unroll
-    for (int t = 0; t < TR::NT; ++t) A[t] *= U;
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int bb = a; bb < NB; ++bb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float f = Fyy;
+                if (bb == NB - 1) {
+                    const bool rrow = a == NB - 1 && Mfma<float>::row(g, r) == caug;
+                    const bool rcol = c == caug;
+                    f = rrow ? (rcol ? Frr : Fyr) : (rcol ? Fyr : Fyy);
+                }
+                A[TR::id(a, bb)][r] *= f;
+            }
 }
 
 // Regularise, optionally form the gradient 2 (A x_in - v), factorise, solve

@@ -1,0 +1,130 @@
+"""GPU parity of the FP32 half-sweep's Gram on FP16 MFMAs (two-term splits of
+the rows scaled by a power of two chosen from max |Y| and each chunk's
+largest rating) against the FP64 oracle's row solve of Eq. (3).
+
+The scale must keep every split value inside the FP16 range and its low
+part normal whatever the magnitudes: factor entries from 1e-6 to 1e4,
+ratings from 1e-3 to 1e5, chunks of one row with very different ratings
+(each chunk picks its own scale, the partial Grams are summed unscaled),
+the augmented rating slot at every lane position (n_f = 16 b + k), and
+fold-in against fixed item factors.  Tolerances are the FP32 ones of the
+other half-sweep tests: 1e-4 per row, 2e-5 on the whole factor.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1508_03110_amd.solver import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def r32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def rowrel(a, b):
+    num = np.linalg.norm(a - b, axis=1)
+    den = np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+    return float(np.max(num / den)) if a.shape[0] else 0.0
+
+
+def fro(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def problem(n_f, seed, y_scale=1.0, r_scale=1.0, n_u=90, n_m=300, lam=0.05, long_rows=False):
+    """Users with 1..200 ratings (a few with 260..300 when long_rows) over
+    n_m items; factors N(0, 0.3) * y_scale, ratings in {0.5 .. 5} * r_scale."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(1, 201, n_u)
+    if long_rows:
+        lens[:6] = rng.integers(260, 301, 6)
+    rows, cols = [], []
+    for u, L in enumerate(lens):
+        rows.append(np.full(L, u))
+        cols.append(rng.choice(n_m, size=int(L), replace=False))
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    vals = rng.integers(1, 11, rows.size) / 2.0 * r_scale
+    R = synth.csr_from_pairs(rows, cols, vals, n_u, n_m)
+    U0 = rng.normal(0, 0.3, (n_u, n_f)) * y_scale
+    M0 = rng.normal(0, 0.3, (n_m, n_f)) * y_scale
+    return synth.Problem("split", R, synth.transpose(R), n_f, lam, U0, M0, seed, {})
+
+
+def sweep_u(ctx, P, chunk=0, ld=None):
+    from paper_1508_03110_amd.solver import DeviceProblem
+    DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32, chunk=chunk, ld=ld)
+    Y = DP.pack(np.zeros((P.n_u, P.n_f)), r32(P.M0))
+    X = torch.full((P.n_u, DP.ld), float("nan"), dtype=torch.float32, device=ctx.torch_device)
+    DP.sweep("U", DP.M(Y), X)
+    torch.cuda.synchronize()
+    return X[:, :P.n_f].cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("y_scale,r_scale", [(1.0, 1.0), (1e-6, 1.0), (1e4, 1.0), (1.0, 1e5),
+                                             (1e-3, 1e-3), (1e3, 1e-3)])
+def test_magnitudes(ctx, y_scale, r_scale):
+    """Factor and rating magnitudes far from 1 in both directions (lambda
+    scaled with y_scale^2 so the regulariser keeps its weight)."""
+    P = problem(100, seed=3, y_scale=y_scale, r_scale=r_scale)
+    P.lam = 0.05 * y_scale * y_scale
+    ref = oracle.half_sweep(P.R, r32(P.M0), P.lam)
+    got = sweep_u(ctx, P)
+    assert np.all(np.isfinite(got))
+    assert rowrel(got, ref) <= 1e-4 and fro(got, ref) <= 2e-5
+
+
+@pytest.mark.parametrize("n_f", [1, 15, 16, 17, 31, 47, 48, 50, 63, 95, 100, 111, 112, 127, 143])
+def test_rating_slot_at_every_lane(ctx, n_f):
+    """n_f = 16 b + k puts the augmented rating at lane k of the last block
+    (k = 15: the last block holds only the rating)."""
+    P = problem(n_f, seed=n_f)
+    ref = oracle.half_sweep(P.R, r32(P.M0), P.lam)
+    got = sweep_u(ctx, P)
+    assert rowrel(got, ref) <= 1e-4 and fro(got, ref) <= 2e-5
+
+
+@pytest.mark.parametrize("chunk", [32, 40, 100])
+def test_split_rows_with_different_scales(ctx, chunk):
+    """Rows split over chunks whose ratings differ by 1e4 (each chunk scales
+    by its own largest rating) and padded rows (ld = 104)."""
+    P = problem(100, seed=7, long_rows=True)
+    vals = P.R.values.copy()
+    for u in range(6):  # the long rows: the first 64 ratings 1e4 times larger
+        b = P.R.indptr[u]
+        vals[b:b + 64] *= 1e4
+    R = synth.Csr(P.R.n_rows, P.R.n_cols, P.R.indptr, P.R.indices, vals.astype(np.float32))
+    P = synth.Problem("split", R, synth.transpose(R), P.n_f, P.lam, P.U0, P.M0, 7, {})
+    ref = oracle.half_sweep(P.R, r32(P.M0), P.lam)
+    got = sweep_u(ctx, P, chunk=chunk, ld=104)
+    assert rowrel(got, ref) <= 1e-4 and fro(got, ref) <= 2e-5
+    # the same rows without splitting agree to the same tolerance
+    whole = sweep_u(ctx, P)
+    assert rowrel(whole, ref) <= 1e-4
+
+
+def test_fold_in_against_large_item_factors(ctx):
+    """fold_in (no plan: the scale of M is taken in the same call) with item
+    factors of magnitude 1e3."""
+    from paper_1508_03110_amd.solver import fold_in
+    P = problem(64, seed=5, y_scale=1e3, n_u=40)
+    lam = 0.05 * 1e6
+    M = torch.as_tensor(r32(P.M0), dtype=torch.float32).to(ctx.torch_device)
+    U, st = fold_in(ctx, M, lam, P.R, P.n_f)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    ref = oracle.fold_in(r32(P.M0), P.R, lam)
+    got = U[:, :P.n_f].cpu().numpy().astype(np.float64)
+    assert rowrel(got, ref) <= 1e-4
