@@ -44,6 +44,9 @@ __device__ __forceinline__ T delem(const typename DVec<T, VW>::type &v, int e) {
     }
 }
 
+// Rated rows read per batch in the output loop.
+constexpr int kOutBatch = 8;
+
 // Wavefronts per SIMD asked of the compiler: the small systems need few
 // registers, so more rows are resident to hide the gathers and the pivot
 // chain.
@@ -90,6 +93,55 @@ __device__ __forceinline__ void dual_consume(typename Mfma<T>::acc4 (&A)[Tri<NBD
 #pragma unroll
             for (int q = p; q < NBD; ++q)
                 A[Tri<NBD>::id(p, q)] = Mfma<T>::mma(a[p], a[q], A[Tri<NBD>::id(p, q)]);
+    }
+}
+
+// x = Y_I^T z (z in xs) and, with grow, g = 2 Y_I^T (e - r) + 2 lambda n x_at;
+// lane k owns factor columns k + 64 h, h < NH.  The rated rows are read
+// again (from L2: the Gram has just read them) in batches of kOutBatch, all
+// loads of a batch in flight together (one load per step of the sum would
+// wait a full memory latency per rating).
+template <typename T, int NH>
+__device__ __forceinline__ void dual_output(const T *__restrict__ Y, const int32_t *ish,
+                                            const T *xs, const T *esh, const T *rsh, int n,
+                                            int n_f, int ld, T reg2, const T *xat, T *xrow,
+                                            T *grow, bool bad) {
+    const int lane = threadIdx.x & 63;
+    T ux[NH], gx[NH];
+    int kc[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        ux[h] = T(0);
+        gx[h] = T(0);
+        kc[h] = min(lane + kWave * h, n_f - 1);
+    }
+    for (int a0 = 0; a0 < n; a0 += kOutBatch) {
+        T y[kOutBatch][NH];
+#pragma unroll
+        for (int u = 0; u < kOutBatch; ++u) {
+            const T *yr = Y + (int64_t)ish[min(a0 + u, n - 1)] * ld;
+#pragma unroll
+            for (int h = 0; h < NH; ++h) y[u][h] = yr[kc[h]];
+        }
+#pragma unroll
+        for (int u = 0; u < kOutBatch; ++u) {
+            const int a = a0 + u;
+            const T za = a < n ? xs[a] : T(0);
+            const T ea = (grow && a < n) ? esh[a] - rsh[a] : T(0);
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                ux[h] += za * y[u][h];
+                gx[h] += ea * y[u][h];
+            }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        const int k = lane + kWave * h;
+        if (k < n_f) {
+            if (grow) grow[k] = T(2) * gx[h] + reg2 * xat[k];
+            xrow[k] = bad ? T(NAN) : ux[h];
+        }
     }
 }
 
@@ -195,30 +247,15 @@ __global__ __launch_bounds__(64, (DualOcc<T, NBD>::waves)) void sweep_dual_kerne
     });
     back_solve<T, NBD, false>(A, n, ys, xs, Yinv);  // xs[0..n) = K^{-1} r, then zeros
 
-    // ---- x = Y_I^T z, g = 2 Y_I^T (e - r) + 2 lambda n x_at; lane k owns
-    // factor columns k, k + 64
+    // ---- x = Y_I^T z, g = 2 Y_I^T (e - r) + 2 lambda n x_at
     const T reg2 = T(2) * lambda * (T)n;
-    for (int k = lane; k < n_f; k += kWave) {
-        T u0 = T(0), u1 = T(0), g0 = T(0), g1 = T(0);
-        int a = 0;
-        for (; a + 1 < n; a += 2) {
-            const T y0 = Y[(int64_t)ish[a] * ld + k];
-            const T y1 = Y[(int64_t)ish[a + 1] * ld + k];
-            u0 += xs[a] * y0;
-            u1 += xs[a + 1] * y1;
-            if (want_g) {
-                g0 += (esh[a] - rsh[a]) * y0;
-                g1 += (esh[a + 1] - rsh[a + 1]) * y1;
-            }
-        }
-        if (a < n) {
-            const T y0 = Y[(int64_t)ish[a] * ld + k];
-            u0 += xs[a] * y0;
-            if (want_g) g0 += (esh[a] - rsh[a]) * y0;
-        }
-        if (want_g) grad_out[row * (int64_t)ld + k] = T(2) * (g0 + g1) + reg2 * xat[k];
-        xrow[k] = bad ? T(NAN) : u0 + u1;
-    }
+    T *grow = want_g ? grad_out + row * (int64_t)ld : nullptr;
+    if (n_f <= kWave)
+        dual_output<T, 1>(Y, ish, xs, esh, rsh, n, n_f, ld, reg2, xat, xrow, grow, bad);
+    else if (n_f <= 2 * kWave)
+        dual_output<T, 2>(Y, ish, xs, esh, rsh, n, n_f, ld, reg2, xat, xrow, grow, bad);
+    else
+        dual_output<T, 3>(Y, ish, xs, esh, rsh, n, n_f, ld, reg2, xat, xrow, grow, bad);
     if (lane == 0 && bad && bad_row) atomicMin((unsigned long long *)bad_row, (unsigned long long)row);
 }
 
