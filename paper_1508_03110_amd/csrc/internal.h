@@ -57,14 +57,12 @@ __device__ inline double readlane(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// 1/sqrt(d) for d > 0: hardware reciprocal square root refined by Newton
-// steps y <- y (3 - d y^2) / 2 (one for FP32, two for FP64), accurate to a
-// few units in the last place; avoids the long IEEE sqrt and divide sequences
-// on the Cholesky pivots.
-__device__ inline float inv_sqrt(float d) {
-    float y = __builtin_amdgcn_rsqf(d);
-    return y * (1.5f - 0.5f * d * y * y);
-}
+// 1/sqrt(d) for d > 0 on the Cholesky pivots, avoiding the long IEEE sqrt
+// and divide sequences.  FP32: the hardware reciprocal square root
+// (v_rsq_f32, about 1 ulp).  FP64: the FP32 estimate refined by three Newton
+// steps y <- y (3 - d y^2) / 2, accurate to a few units in the last place.
+// d <= 0 gives a NaN or an infinity (the caller reports the pivot).
+__device__ inline float inv_sqrt(float d) { return __builtin_amdgcn_rsqf(d); }
 __device__ inline double inv_sqrt(double d) {
     double y = (double)__builtin_amdgcn_rsqf((float)d);
     y = y * (1.5 - 0.5 * d * y * y);

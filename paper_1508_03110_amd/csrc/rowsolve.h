@@ -91,11 +91,11 @@ __device__ __forceinline__ bool cholesky_blocked(typename Mfma<T>::acc4 (&A)[Tri
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
             if (16 * kb + kk < n_f) {
-                T d = readlane(p[kk], kk);
-                if (!(d > T(0))) {
-                    bad = true;
-                    d = T(1);
-                }
+                // a pivot that is not positive marks the row; the NaN or
+                // infinity it leaves in the factor reaches only this row,
+                // whose output is replaced by NaN
+                const T d = readlane(p[kk], kk);
+                bad |= !(d > T(0));
                 p[kk] *= inv_sqrt(d);
                 T rk[16];  // row kk of the factor, broadcast first, then used
 #pragma unroll
