@@ -301,11 +301,14 @@ __global__ __launch_bounds__(64) void grad_split_kernel(
 //   (r - u.m)^2 = d^2 - 2 d a1 alpha + (a1^2 - 2 d a2) alpha^2 + 2 a1 a2 alpha^3 + a2^2 alpha^4.
 // The first chunk of each user row also adds that user's regulariser
 // lambda n_i ||xu + alpha pu||^2.  part[5q + n] is the chunk's share of C_n.
+// XU, PU: user rows (stride ld); XM, PM: the gathered item rows (stride
+// ldm, e.g. 2 ld when they are the two halves of interleaved [x_j | p_j]
+// rows).
 template <typename T, int VEC, int NV, int L, bool PERSIST>
 __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void coeff_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ XU, const T *__restrict__ XM,
-    const T *__restrict__ PU, const T *__restrict__ PM, int n_f, int ld, double lambda,
+    const T *__restrict__ PU, const T *__restrict__ PM, int n_f, int ld, int ldm, double lambda,
     int64_t n_chunks, const int32_t *__restrict__ chunk_row,
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
     double *__restrict__ part, const double *__restrict__ pred) {
@@ -359,8 +362,8 @@ __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void coeff_chunk
 #pragma unroll
         for (int k = 0; k < D - 1; ++k) {
             const int j = idx[pos(k)];
-            gather_row<T, VEC, NV, L>(xs[k], XM, j, ld, c, cl);
-            gather_row<T, VEC, NV, L>(ps[k], PM, j, ld, c, cl);
+            gather_row<T, VEC, NV, L>(xs[k], XM, j, ldm, c, cl);
+            gather_row<T, VEC, NV, L>(ps[k], PM, j, ldm, c, cl);
             rv[k] = val[pos(k)];
         }
 #pragma unroll
@@ -369,8 +372,8 @@ __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void coeff_chunk
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int slot = (k + D - 1) % D;
-                gather_row<T, VEC, NV, L>(xs[slot], XM, jq[slot], ld, c, cl);
-                gather_row<T, VEC, NV, L>(ps[slot], PM, jq[slot], ld, c, cl);
+                gather_row<T, VEC, NV, L>(xs[slot], XM, jq[slot], ldm, c, cl);
+                gather_row<T, VEC, NV, L>(ps[slot], PM, jq[slot], ldm, c, cl);
                 rv[slot] = val[pos(s0 + k + D - 1)];
                 jq[slot] = idx[pos(s0 + k + 2 * D - 1)];
                 if (s0 + k < ngr) step(xs[k], ps[k], b + (s0 + k) * GR + g < e, rv[k]);
@@ -407,6 +410,26 @@ __global__ __launch_bounds__(64, (kPassWaves<T, VEC, PERSIST>)) void coeff_chunk
         o[3] = c3;
         o[4] = c4;
     }
+    }
+}
+
+// XP[j] = [XM[j] | PM[j]] (the first n_f columns of each, row stride 2 ld):
+// the coefficient pass gathers both rows of every rated item, and one
+// contiguous pair touches fewer cache lines and DRAM pages than two rows in
+// separate arrays (bitwise the same arithmetic).
+template <typename T>
+__global__ __launch_bounds__(256) void pair_rows_kernel(const T *__restrict__ XM,
+                                                        const T *__restrict__ PM, int64_t n,
+                                                        int n_f, int ld, T *__restrict__ XP,
+                                                        const double *__restrict__ pred) {
+    if (pred && *pred == 0.0) return;
+    const int lane = threadIdx.x & 63;
+    for (int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); j < n;
+         j += (int64_t)gridDim.x * 4) {
+        for (int r = lane; r < 2 * n_f; r += kWave) {
+            const int half = r >= n_f, col = r - half * n_f;
+            XP[j * 2 * ld + half * ld + col] = (half ? PM : XM)[j * ld + col];
+        }
     }
 }
 
@@ -556,12 +579,28 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
     const int64_t rows = pR->n_chunks + kItemBlocks;
     const size_t need = (size_t)(rows * 5 + kSumStageDoubles);
     double *part = fixed;
+    // gathered item rows: [x_j | p_j] pairs in workspace, or (fixed scratch)
+    // the two arrays as given
+    const T *GX = M, *GP = PM;
+    int ldm = ld;
     if (fixed) {
         if (need > fixed_doubles) return ALS_E_BUDGET;
     } else {
+        const size_t part_bytes = align_up(need * sizeof(double), 256);
+        const size_t pair_bytes = (size_t)Rt->n_rows * 2 * ld * sizeof(T);
         int err = ALS_OK;
-        part = (double *)ctx->workspace(need * sizeof(double), s, &err);
-        if (!part) return err;
+        char *ws = (char *)ctx->workspace(part_bytes + pair_bytes, s, &err);
+        if (!ws) return err;
+        part = (double *)ws;
+        T *XP = (T *)(ws + part_bytes);
+        if (Rt->n_rows > 0) {
+            const unsigned blocks = (unsigned)std::min<int64_t>((Rt->n_rows + 3) / 4, 8192);
+            hipLaunchKernelGGL(pair_rows_kernel<T>, dim3(blocks), dim3(256), 0, s, M, PM,
+                               Rt->n_rows, n_f, ld, XP, pred);
+        }
+        GX = XP;
+        GP = XP + ld;
+        ldm = 2 * ld;
     }
     if (pR->n_chunks) {
         // a predicated pass (launched in every iteration, needed only after a
@@ -573,7 +612,7 @@ int run_coeffs(Ctx *ctx, const Plan *pR, const als_csr *R, const als_csr *Rt, co
             grid = (unsigned)std::min<int64_t>(pR->n_chunks, (int64_t)ctx->num_cu * 16);
 #define ALS_COEF(P)                                                                             \
     hipLaunchKernelGGL((coeff_chunks_kernel<T, VEC, NV, L, P>), dim3(grid), dim3(kWave), 0, s,       \
-                       R->indptr, R->indices, R->values, U, M, PU, PM, n_f, ld, lambda,         \
+                       R->indptr, R->indices, R->values, U, GX, PU, GP, n_f, ld, ldm, lambda,   \
                        pR->n_chunks, pR->chunk_row, pR->chunk_begin, pR->chunk_len, part, pred)
         if (persist)
             ALS_COEF(true);
