@@ -505,6 +505,9 @@ def c3_bench(ctx, steps=20, gtol=1e-6, max_iter=400):
     return out
 
 
+C2_LD = 64  # row stride of the factors at the billion-rating shape (n_f = 50)
+
+
 def c2_bench(ctx, steps=5, als_steps=3):
     """Billion-rating configuration: 10M users x 1M items, exactly 1e9 ratings
     (power-law user activity on [1, 50000], Zipf 1.1 items), n_f = 50,
@@ -524,11 +527,14 @@ def c2_bench(ctx, steps=5, als_steps=3):
     Rtd = DeviceCsr(ctx, R.indptr_t, R.indices_t, R.values_t, R.n_u)
     meta = dict(R.meta)
     del R
-    DP = DeviceProblem(ctx, Rd, Rtd, n_f, lam, torch.float32)
+    # factor rows padded to 64 floats (256 bytes): every gathered row is two
+    # whole 128-byte cache lines instead of straddling three more than half
+    # of the time at a 200-byte stride
+    DP = DeviceProblem(ctx, Rd, Rtd, n_f, lam, torch.float32, ld=C2_LD)
     x0 = DP.pack(U0, M0)
     del U0, M0
     out = {"workload": "10M x 1M, 1e9 ratings, n_f=50", "n_u": DP.n_u, "n_m": DP.n_m,
-           "nnz": DP.R.nnz, "n_f": n_f, "lambda": lam, "generator": meta,
+           "nnz": DP.R.nnz, "n_f": n_f, "ld": C2_LD, "lambda": lam, "generator": meta,
            "setup_seconds": round(time.perf_counter() - t0, 1)}
     log("C2 problem on device (%.1f s); plans R %s R^T %s" % (time.perf_counter() - t0, DP.R.info(), DP.Rt.info()))
     out["tuning"] = tune.tune(DP, x0, log=log)

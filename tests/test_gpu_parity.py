@@ -381,6 +381,40 @@ def test_als_ncg_20_iterations_lockstep(ctx, c0, dtype, tol):
     assert gpu.f < fa[-1]  # ALS-NCG ahead of ALS after the same number of iterations
 
 
+@pytest.mark.parametrize("dtype,ld,tol", [(torch.float64, 16, 1e-10), (torch.float32, 16, 1e-5)])
+@pytest.mark.parametrize("mode", ["host", "device", "graph"])
+def test_als_ncg_with_padded_rows(ctx, c0, dtype, ld, tol, mode):
+    """Algorithm 2 with factor rows padded past n_f (n_f = 10, ld = 16, as the
+    billion-rating benchmark pads n_f = 50 to 64): every NCG vector carries
+    the padding columns, which must stay zero and out of every dot product;
+    f(x_k) tracks the oracle for 8 iterations driven from the host, from the
+    device, and as replays of the captured iteration."""
+    from paper_1508_03110_amd.solver import AlsNcg
+    DP = dev_problem(ctx, c0, dtype, ld=ld)
+    assert DP.ld == ld
+    cast = (lambda a: a) if dtype == torch.float64 else r32
+    U0, M0 = cast(c0.U0), cast(c0.M0)
+    gpu = AlsNcg(DP).init(U0, M0)
+    o = oracle.NcgOracle(c0.R, c0.Rt, c0.n_f, c0.lam)
+    s = o.init(U0, M0)
+    for k in range(8):
+        if mode == "host":
+            gpu.step()
+        elif mode == "device" or k == 0:
+            gpu.step_device()  # (graph mode: the eager step sizes the workspace)
+            gpu.read_state()
+        else:
+            if k == 1:
+                gpu.capture()
+            gpu.replay()
+            gpu.read_state()
+        o.step(s)
+        assert gpu.n_trials == s.trials, k
+        assert gpu.f == pytest.approx(o.f(s.x), rel=tol), k
+    X = gpu.x.view(-1, ld).cpu().numpy()
+    assert np.all(X[:, c0.n_f:] == 0.0)
+
+
 def test_exact_quartic_minimiser_matches_oracle(ctx):
     """ncg_linesearch_exact against oracle.quartic_min (numpy's polynomial
     roots) on random quartics, double wells, a vanishing quartic term and an
