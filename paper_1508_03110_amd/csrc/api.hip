@@ -124,7 +124,7 @@ int als_ctx_create(als_ctx **out, int device) {
     }
     c->scratch = (double *)sp;
     c->scratch_doubles = alsncg::kScratchDoubles;
-    if (hipMalloc((void **)&c->ybits, 256) != hipSuccess) {
+    if (hipMalloc((void **)&c->ybits, alsncg::kAbsMaxWords * sizeof(unsigned)) != hipSuccess) {
         delete c;
         return ALS_E_NOMEM;
     }

@@ -209,8 +209,9 @@ struct Ctx {
     // device (looked up once at creation) and its size in doubles
     double *scratch = nullptr;
     size_t scratch_doubles = 0;
-    // device word for the FP32 half-sweep's scale (bits of max |Y|),
-    // rewritten before every FP32 half-sweep on this context
+    // device words for the FP32 half-sweep's scale (ybits[0]: bits of max
+    // |Y|; kAbsMaxWords in all), rewritten before every FP32 half-sweep on
+    // this context
     unsigned *ybits = nullptr;
     // Returns workspace of at least `bytes` (grows; synchronises before freeing).
     void *workspace(size_t bytes, hipStream_t stream, int *err);
@@ -236,9 +237,12 @@ int launch_sweep_dual(const Plan *plan, const als_csr *R, const void *Y, void *X
 int launch_fold_in(Ctx *ctx, const void *M, int64_t n_items, int n_f, int ld, double lambda,
                    als_dtype dt, int64_t n_req, const int64_t *indptr, const int32_t *items,
                    const float *vals, void *U_out, int32_t *status, hipStream_t s);
-// *out = bit pattern of max |Y| over the n x n_f block of Y (row stride ld):
-// the scale of the FP32 half-sweep's FP16-split Gram.  Two launches (a
-// fill, then an integer max), stream-ordered, no memset.
+// out[0] = bit pattern of max |Y| over the n x n_f block of Y (row stride
+// ld): the scale of the FP32 half-sweep's FP16-split Gram.  out holds
+// kAbsMaxWords words (out[1..] per-workgroup maxima); two launches,
+// stream-ordered, no memset.
+constexpr int kAbsMaxParts = 2048;
+constexpr int kAbsMaxWords = 1 + kAbsMaxParts;
 int launch_abs_max_bits(const float *Y, int64_t n, int n_f, int ld, unsigned *out, hipStream_t s);
 // Planned half-sweep over a caller-built plan with caller-provided split-K
 // workspace (sweep_partial_bytes per split chunk) and per-row status (empty

@@ -369,7 +369,7 @@ int als_server_create(als_ctx *ctx, const void *M, int64_t n_items, int n_f, int
     S->slots.resize(cfg->max_inflight);
     int rc = ALS_OK;
     if (dt == ALS_F32) {
-        if (hipMalloc((void **)&S->ybits, 256) != hipSuccess) {
+        if (hipMalloc((void **)&S->ybits, kAbsMaxWords * sizeof(unsigned)) != hipSuccess) {
             delete S;
             return ALS_E_NOMEM;
         }

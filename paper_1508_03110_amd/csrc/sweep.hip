@@ -589,17 +589,22 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_split_kernel(
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 __global__ void set_u32_kernel(unsigned *p, unsigned v) { *p = v; }
 
-// *out = max(*out, bit pattern of max |Y|) over the n x n_f block of Y (row
-// stride ld): the integer order of the bit patterns of non-negative floats
-// is their numeric order (NaN above infinity), so the maximum is exact and
-// independent of the schedule.  A wavefront takes 8 rows per step, lanes
-// over the columns (n_f <= 192); loads are clamped into the block.
+// Bit pattern of max |Y| over the n x n_f block of Y (row stride ld): the
+// integer order of the bit patterns of non-negative floats is their numeric
+// order (NaN above infinity), so the maximum is exact and independent of the
+// schedule.  A wavefront takes 8 rows per step, lanes over the columns
+// (n_f <= 192), loads clamped into the block; each workgroup writes its
+// maximum to part[blockIdx.x] and one more workgroup reduces the parts (no
+// atomics: thousands of them on one address serialise at L2).
 constexpr int kAbsMaxRows = 8;
 __global__ __launch_bounds__(256) void abs_max_bits_kernel(const float *__restrict__ Y, int64_t n,
-                                                           int n_f, int ld, unsigned *out) {
-    const int lane = threadIdx.x & 63;
+                                                           int n_f, int ld,
+                                                           unsigned *__restrict__ part) {
+    __shared__ unsigned red[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int nq = (n_f + kWave - 1) / kWave;
     unsigned m = 0u;
     for (int64_t r0 = w0 * kAbsMaxRows; r0 < n; r0 += nw * kAbsMaxRows) {
         unsigned v[kAbsMaxRows][3];
@@ -608,7 +613,7 @@ __global__ __launch_bounds__(256) void abs_max_bits_kernel(const float *__restri
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int64_t r = min(r0 + u, n - 1);
-                const int col = min(lane + kWave * q, n_f - 1);
+                const int col = min(lane + kWave * min(q, nq - 1), n_f - 1);
                 v[u][q] = __float_as_uint(Y[r * ld + col]) & 0x7fffffffu;
             }
 #pragma unroll
@@ -618,7 +623,22 @@ __global__ __launch_bounds__(256) void abs_max_bits_kernel(const float *__restri
     }
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
-    if (lane == 0) atomicMax(out, m);
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void abs_max_final_kernel(const unsigned *__restrict__ part,
+                                                            int n_part, unsigned *out) {
+    __shared__ unsigned red[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned m = 0u;
+    for (int k = threadIdx.x; k < n_part; k += blockDim.x) m = max(m, part[k]);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = max(max(red[0], red[1]), max(red[2], red[3]));
 }
 
 // FP32: ybits holds the bits of max |Y| (abs_max_bits_kernel); null: it is
@@ -743,11 +763,16 @@ int dispatch_sweep(Ctx *ctx, const Plan *plan, const als_csr *R, const void *Y,
 }  // namespace
 
 int launch_abs_max_bits(const float *Y, int64_t n, int n_f, int ld, unsigned *out, hipStream_t s) {
-    hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(1), 0, s, out, 0u);
-    if (Y && n > 0 && n_f > 0) {
+    if (!Y || n <= 0 || n_f <= 0) {
+        hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(1), 0, s, out, 0u);
+    } else {
         const int64_t per_block = 4 * kAbsMaxRows;
-        const unsigned blocks = (unsigned)std::min<int64_t>((n + per_block - 1) / per_block, 8192);
-        hipLaunchKernelGGL(abs_max_bits_kernel, dim3(blocks), dim3(256), 0, s, Y, n, n_f, ld, out);
+        const unsigned blocks =
+            (unsigned)std::min<int64_t>((n + per_block - 1) / per_block, kAbsMaxParts);
+        hipLaunchKernelGGL(abs_max_bits_kernel, dim3(blocks), dim3(256), 0, s, Y, n, n_f, ld,
+                           out + 1);
+        hipLaunchKernelGGL(abs_max_final_kernel, dim3(1), dim3(256), 0, s, out + 1, (int)blocks,
+                           out);
     }
     return hipGetLastError() == hipSuccess ? ALS_OK : ALS_E_HIP;
 }
