@@ -55,11 +55,17 @@ def sweep_flops_binned(counts, n_f, dual_max):
 
 
 def kernel_source_hash():
+    """sha256 (first 16 hex) of the half-sweep's sources with // comments,
+    trailing blanks and empty lines removed: the code the counters were
+    taken on, not its commentary."""
     import hashlib
     m = hashlib.sha256()
     for f in ("sweep.hip", "sweep_dual.hip", "internal.h", "rowsolve.h"):
-        with open(os.path.join(ROOT, "paper_1508_03110_amd", "csrc", f), "rb") as fh:
-            m.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1508_03110_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    m.update(code.encode() + b"\n")
     return m.hexdigest()[:16]
 
 

@@ -1,13 +1,16 @@
 // ALS half-sweep and fold-in kernels (Eq. (3)/(4) of the paper, Section III-A;
 // Cholesky solve as in Section V-B).
 //
-// One wavefront owns one chunk of one row.  For every group of 4 ratings the
-// wave gathers the 4 fixed-side factor rows straight into registers, one
-// column per lane, and issues one MFMA per upper-triangular 16x16 tile of the
-// Gram matrix.  The gathered row is AUGMENTED with the rating value in column
-// n_f, so the same tiles also accumulate v_i = sum r_ij y_j (column n_f) and
-// sum r_ij^2; factorising the augmented matrix performs the forward
-// substitution R^T z = v for free (z ends up in column n_f of the factor).
+// One wavefront owns one chunk of one row.  The wave gathers the fixed-side
+// factor rows of the chunk's ratings straight into registers and
+// accumulates the upper-triangular 16x16 tiles of the Gram matrix on the
+// MFMA: FP32 in groups of 32 ratings on v_mfma_f32_16x16x32_f16 from
+// two-term FP16 splits (gram_split), FP64 in groups of 4 on the FP64
+// 16x16x4 MFMA (gram_accumulate).  The gathered row is AUGMENTED with the
+// rating value in column n_f, so the same tiles also accumulate
+// v_i = sum r_ij y_j (column n_f) and sum r_ij^2; factorising the augmented
+// matrix performs the forward substitution R^T z = v for free (z ends up in
+// column n_f of the factor).
 //
 // Register layout of an accumulator tile (a, b) (rows of block a, columns of
 // block b, a <= b): lane l = 16 g + c holds element (16 a + row(g, r),
@@ -15,7 +18,7 @@
 // g + 4 r for FP64).  The blocked right-looking Cholesky A = R^T R
 // works on that layout directly:
 //   * the 16 pivots of block row kb are processed on the VALU, one row of R
-//     at a time, the pivot row being broadcast through LDS;
+//     at a time, the pivot row being broadcast with readlane;
 //   * the trailing update A(a, b) -= R(kb, a)^T R(kb, b) is 4 MFMAs per tile,
 //     again feeding accumulator registers as MFMA operands (the sum over the
 //     16 rows of block kb is order-free).
