@@ -592,10 +592,11 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_split_kernel(
 __global__ void set_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 __global__ void set_u32_kernel(unsigned *p, unsigned v) { *p = v; }
 
-// Bit pattern of max |Y| over the n x n_f block of Y (row stride ld): the
-// integer order of the bit patterns of non-negative floats is their numeric
-// order (NaN above infinity), so the maximum is exact and independent of the
-// schedule.  A wavefront takes 8 rows per step, lanes over the columns
+// Bit pattern of the largest finite |y| over the n x n_f block of Y (row
+// stride ld): the integer order of the bit patterns of non-negative finite
+// floats is their numeric order, so the maximum is exact and independent of
+// the schedule (a non-finite entry poisons only the rows that rate it, not
+// the scale of every row).  A wavefront takes 8 rows per step, lanes over the columns
 // (n_f <= 192), loads clamped into the block; each workgroup writes its
 // maximum to part[blockIdx.x] and one more workgroup reduces the parts (no
 // atomics: thousands of them on one address serialise at L2).
@@ -617,7 +618,8 @@ __global__ __launch_bounds__(256) void abs_max_bits_kernel(const float *__restri
             for (int q = 0; q < 3; ++q) {
                 const int64_t r = min(r0 + u, n - 1);
                 const int col = min(lane + kWave * min(q, nq - 1), n_f - 1);
-                v[u][q] = __float_as_uint(Y[r * ld + col]) & 0x7fffffffu;
+                const unsigned a = __float_as_uint(Y[r * ld + col]) & 0x7fffffffu;
+                v[u][q] = a < 0x7f800000u ? a : 0u;  // non-finite entries do not set the scale
             }
 #pragma unroll
         for (int u = 0; u < kAbsMaxRows; ++u)

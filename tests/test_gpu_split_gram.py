@@ -128,3 +128,48 @@ def test_fold_in_against_large_item_factors(ctx):
     ref = oracle.fold_in(r32(P.M0), P.R, lam)
     got = U[:, :P.n_f].cpu().numpy().astype(np.float64)
     assert rowrel(got, ref) <= 1e-4
+
+
+def test_non_finite_factor_row_stays_local(ctx):
+    """An item row holding NaN and one holding infinity: the users who rated
+    them get NaN rows and are reported by bad_row; every other user matches
+    the oracle (the non-finite entries do not set the scale of the others)."""
+    from paper_1508_03110_amd.solver import DeviceProblem
+    P = problem(100, seed=13)
+    M = r32(P.M0)
+    M[7, 3] = np.nan
+    M[11, 50] = np.inf
+    DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32)
+    X = torch.zeros((P.n_u, P.n_f), dtype=torch.float32, device=ctx.torch_device)
+    bad = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    DP.sweep("U", torch.as_tensor(M, dtype=torch.float32).to(ctx.torch_device), X, bad_row=bad)
+    got = X.cpu().numpy().astype(np.float64)
+    touched = np.zeros(P.n_u, dtype=bool)
+    for u in range(P.n_u):
+        items = P.R.indices[P.R.indptr[u]:P.R.indptr[u + 1]]
+        touched[u] = np.any((items == 7) | (items == 11))
+    assert touched.any() and (~touched).any()
+    assert np.all(~np.isfinite(got[touched]).all(axis=1))
+    assert int(bad.item()) == int(np.flatnonzero(touched)[0])
+    clean = r32(P.M0)
+    ref = oracle.half_sweep(P.R, clean, P.lam)
+    assert rowrel(got[~touched], ref[~touched]) <= 1e-4
+
+
+def test_not_spd_row_fp32(ctx):
+    """lambda = 0 and rank-deficient rows in the FP32 path (FP16-split Gram,
+    hardware reciprocal square root on the pivots): bad_row names the first
+    one, its output is NaN, the full-rank row is solved."""
+    rows = np.array([0, 0, 1, 1, 1, 2, 2])
+    cols = np.array([0, 1, 0, 1, 2, 1, 2])
+    R = synth.csr_from_pairs(rows, cols, np.ones(7), 3, 3)
+    P = synth.Problem("tiny", R, synth.transpose(R), 3, 0.0, np.zeros((3, 3)), np.eye(3), 0)
+    from paper_1508_03110_amd.solver import DeviceProblem
+    DP = DeviceProblem(ctx, P.R, P.Rt, 3, 0.0, torch.float32)
+    X = torch.zeros((3, 3), dtype=torch.float32, device=ctx.torch_device)
+    bad = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    DP.sweep("U", torch.eye(3, dtype=torch.float32, device=ctx.torch_device), X, bad_row=bad)
+    assert int(bad.item()) == 0
+    Xg = X.cpu().numpy()
+    assert np.all(np.isnan(Xg[0])) and np.all(np.isnan(Xg[2]))
+    np.testing.assert_allclose(Xg[1], [1.0, 1.0, 1.0], rtol=1e-6)
