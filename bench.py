@@ -792,6 +792,62 @@ def compact(res, full_path):
     return out
 
 
+def gather_probe(reps=10):
+    """How much of each gather-bound phase is the gathers' trip beyond L2:
+    the coefficient pass, the M-block gradient and both half-sweeps (length
+    bound 78 for users) at the 20M-rating shape, timed with the real rating
+    ids and with every id folded into [0, 64) (same work and access count,
+    every gathered row an L2 hit; the results of the folded runs are not
+    used).  Best of 3 rounds of `reps` launches (HIP events)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1508_03110_amd.solver import Context, DeviceProblem
+
+    def t_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = float("inf")
+        for _ in range(3):
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b) / reps)
+        return round(best, 4)
+
+    P = synth.c1_ml20m()
+    ctx = Context(0)
+    out = {"workload": "20M-rating shape, n_f=100, FP32, user bound 78", "reps": reps}
+    for mode in ("real_ids", "ids_folded_into_64_rows"):
+        R, Rt = P.R, P.Rt
+        if mode != "real_ids":
+            R = synth.Csr(R.n_rows, R.n_cols, R.indptr, (R.indices % 64).astype(np.int32), R.values)
+            Rt = synth.Csr(Rt.n_rows, Rt.n_cols, Rt.indptr, (Rt.indices % 64).astype(np.int32),
+                           Rt.values)
+        DP = DeviceProblem(ctx, R, Rt, P.n_f, P.lam, torch.float32)
+        DP.R.set_dual(78)
+        x = DP.pack(P.U0.astype(np.float32), P.M0.astype(np.float32))
+        p = torch.empty_like(x).normal_(0.0, 0.01)
+        g = DP.zeros()
+        C = torch.zeros(5, dtype=torch.float64, device=x.device)
+        X = torch.empty((P.n_u, DP.ld), dtype=torch.float32, device=x.device)
+        Mo = torch.empty((P.n_m, DP.ld), dtype=torch.float32, device=x.device)
+        out[mode] = {
+            "coefficients_ms": t_ms(lambda: DP.coeffs(DP.U(x), DP.M(x), DP.U(p), DP.M(p), C)),
+            "gradient_M_ms": t_ms(lambda: DP.gradient(DP.U(x), DP.M(x), None, DP.M(g), None)),
+            "sweep_U_ms": t_ms(lambda: DP.sweep("U", DP.M(x), X, X_at=DP.U(x), grad_out=DP.U(g))),
+            "sweep_M_ms": t_ms(lambda: DP.sweep("M", DP.U(x), Mo)),
+        }
+        log("gather probe", mode, out[mode])
+        del DP, x, p, g, X, Mo
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -812,7 +868,13 @@ def main():
                          "timing the candidates (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM traffic counters)")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="run only the gather probe: the 20M-rating shape's passes with the real "
+                         "rating ids and with the ids folded into 64 rows (every gather an L2 hit)")
     args = ap.parse_args()
+    if args.gather_probe:
+        print(json.dumps(gather_probe()))
+        return
     if args.calibrate_copy:
         import torch
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
