@@ -217,7 +217,8 @@ int als_plan_set_dual(als_plan *p, int64_t max_len) {
     p->n_dual = n_dual;
     for (int b = 0; b < 8; ++b) p->dual_first[b] = p->dual_count[b] = 0;
     for (int64_t k = (int64_t)nc - n_dual; k < (int64_t)nc; ++k) {
-        const int b = (int)((p->h_len[(size_t)k] + 2 + 15) / 16);
+        const int64_t n = p->h_len[(size_t)k];
+        const int b = n == 1 ? 0 : (int)((n + 2 + 15) / 16);  // bin 0: one rating
         if (p->dual_count[b] == 0) p->dual_first[b] = k;
         ++p->dual_count[b];
     }

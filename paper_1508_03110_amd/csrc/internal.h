@@ -184,8 +184,9 @@ struct Plan {
     int32_t *slot_chunk = nullptr;
     // dual-form bins of the half-sweep (als_plan_set_dual): whole rows of
     // 1 <= n_i <= dual_max ratings are the last n_dual chunks, longest first;
-    // bin b (1 <= b <= kDualMaxBlocks) holds the rows with
-    // ceil((n_i + 2) / 16) = b, chunks dual_first[b] .. + dual_count[b] - 1
+    // bin b (1 <= b <= kDualMaxBlocks) holds the rows with n_i >= 2 and
+    // ceil((n_i + 2) / 16) = b, bin 0 the rows with one rating (closed
+    // form), chunks dual_first[b] .. + dual_count[b] - 1
     int64_t dual_max = 0, n_dual = 0;
     int64_t dual_first[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t dual_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};

@@ -8,7 +8,9 @@
 // Gram (K = Y_I Y_I^T contracts over the n_f factor columns) and a much
 // shorter Cholesky (n_i pivots instead of n_f).  Rows are binned by
 // NBD = ceil((n_i + 2) / 16), the number of 16-wide tiles of their system;
-// one kernel instance per bin, one wavefront per row.
+// one kernel instance per bin, one wavefront per row.  Rows with a single
+// rating take the closed form of the 1 x 1 system instead (sweep_one_kernel,
+// four rows per wavefront).
 //
 // Slots of the dual system: slot a < n_i is the a-th rated row y_a; slot n_i
 // holds the right-hand side r (set after the Gram, so the factorisation
@@ -259,6 +261,58 @@ __global__ __launch_bounds__(64, (DualOcc<T, NBD>::waves)) void sweep_dual_kerne
     if (lane == 0 && bad && bad_row) atomicMin((unsigned long long *)bad_row, (unsigned long long)row);
 }
 
+// Rows with one rating (bin 0): the dual system is 1 x 1, so
+//     x = r y / (y . y + lambda)        (lambda n_i with n_i = 1),
+// and the fused gradient at x_at is 2 (y . x_at - r) y + 2 lambda x_at.
+// Four rows per wavefront, one per 16-lane group: lane c takes columns
+// c, c + 16, ... of its row (16 consecutive elements per load step); the
+// dots are reduced over the group.
+constexpr int kOneCols = 9;  // columns per lane: n_f <= 144
+template <typename T>
+__global__ __launch_bounds__(256) void sweep_one_kernel(
+    const int32_t *__restrict__ idx, const float *__restrict__ val, const T *__restrict__ Y,
+    T *__restrict__ X, int n_f, int ld, T lambda, const int32_t *__restrict__ chunk_row,
+    const int64_t *__restrict__ chunk_begin, int64_t first, int64_t count,
+    const T *__restrict__ X_at, T *__restrict__ grad_out, int64_t *__restrict__ bad_row) {
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    if (t >= count) return;  // whole 16-lane groups leave together
+    const int c = threadIdx.x & 15;
+    const int64_t q = first + t;
+    const int64_t row = chunk_row[q], b = chunk_begin[q];
+    const T r = (T)val[b];
+    const T *y = Y + (int64_t)idx[b] * ld;
+    const T *xat = X_at ? X_at + row * (int64_t)ld : X + row * (int64_t)ld;
+    const bool want_g = grad_out != nullptr;
+    T yv[kOneCols], xv[kOneCols];
+    T yy = T(0), e = T(0);
+#pragma unroll
+    for (int u = 0; u < kOneCols; ++u) {
+        const int k = c + 16 * u;
+        yv[u] = k < n_f ? y[k] : T(0);
+        xv[u] = (want_g && k < n_f) ? xat[k] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kOneCols; ++u) {
+        yy += yv[u] * yv[u];
+        e += yv[u] * xv[u];
+    }
+    yy = sum16(yy);
+    e = sum16(e);
+    const T den = yy + lambda;
+    const bool bad = !(den > T(0));
+    const T s = r / den, ge = T(2) * (e - r), gl = T(2) * lambda;
+    T *xrow = X + row * (int64_t)ld;
+#pragma unroll
+    for (int u = 0; u < kOneCols; ++u) {
+        const int k = c + 16 * u;
+        if (k < n_f) {
+            if (want_g) grad_out[row * (int64_t)ld + k] = ge * yv[u] + gl * xv[u];
+            xrow[k] = bad ? T(NAN) : s * yv[u];
+        }
+    }
+    if (c == 0 && bad && bad_row) atomicMin((unsigned long long *)bad_row, (unsigned long long)row);
+}
+
 template <typename T, int VW>
 int run_dual(const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int ld, T lambda,
              const T *X_at, T *grad_out, int64_t *bad_row, hipStream_t s) {
@@ -268,6 +322,11 @@ int run_dual(const Plan *plan, const als_csr *R, const T *Y, T *X, int n_f, int 
                            dim3(kWave), 0, s, R->indices, R->values, Y, X, n_f, ld, lambda,        \
                            plan->chunk_row, plan->chunk_begin, plan->chunk_len,                    \
                            plan->dual_first[NBD], plan->dual_count[NBD], X_at, grad_out, bad_row);
+    if (plan->dual_count[0] > 0)
+        hipLaunchKernelGGL((sweep_one_kernel<T>), dim3((unsigned)((plan->dual_count[0] + 15) / 16)),
+                           dim3(256), 0, s, R->indices, R->values, Y, X, n_f, ld, lambda,
+                           plan->chunk_row, plan->chunk_begin, plan->dual_first[0],
+                           plan->dual_count[0], X_at, grad_out, bad_row);
     ALS_DUAL_BIN(1)
     ALS_DUAL_BIN(2)
     ALS_DUAL_BIN(3)
