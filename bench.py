@@ -723,6 +723,8 @@ def compact(res, full_path):
     out["f"] = _r(res["f"], 12)
     if "length_bins" in res:
         out["dual_max"] = {k: v["dual_max"] for k, v in res["length_bins"].items()}
+    if "grad_slices" in res:
+        out["grad_slices"] = res["grad_slices"]["best"]["slices"]
     tt = res.get("time_to_tol")
     if tt:
         sm = {"f_gap_tol": tt["f_gap_tol"], "gnorm_over_N_tol": tt["gnorm_over_N_tol"]}
@@ -781,6 +783,8 @@ def compact(res, full_path):
                             "sweep_U_tflops": _r(c2["sweep_U_tflops_eager"]),
                             "dual_max": {k: v["best"].get("dual_max") for k, v in
                                          c2.get("tuning", {}).items()},
+                            "grad_slices": c2.get("tuning", {}).get("M", {}).get("best", {})
+                                             .get("grad_slices"),
                             "phase_ms": {k: _r(v) for k, v in
                                          c2["als_ncg"]["phase_ms_eager_step"].items()}}
         curve = c2.get("speedup_vs_gnorm", {}).get("curve", [])
@@ -798,7 +802,8 @@ def gather_probe(reps=10):
     bound 78 for users) at the 20M-rating shape, timed with the real rating
     ids and with every id folded into [0, 64) (same work and access count,
     every gathered row an L2 hit; the results of the folded runs are not
-    used).  Best of 3 rounds of `reps` launches (HIP events)."""
+    used), and the M-block gradient with the real ids over a plan cut at 8
+    column slices.  Best of 3 rounds of `reps` launches (HIP events)."""
     import numpy as np
     import torch
 
@@ -842,6 +847,11 @@ def gather_probe(reps=10):
             "sweep_U_ms": t_ms(lambda: DP.sweep("U", DP.M(x), X, X_at=DP.U(x), grad_out=DP.U(g))),
             "sweep_M_ms": t_ms(lambda: DP.sweep("M", DP.U(x), Mo)),
         }
+        if mode == "real_ids":  # the gradient over a plan cut at 8 column slices
+            DP.Rt.set_grad_slices(8)
+            out[mode]["gradient_M_8_slices_ms"] = t_ms(
+                lambda: DP.gradient(DP.U(x), DP.M(x), None, DP.M(g), None))
+            DP.Rt.set_grad_slices(0)
         log("gather probe", mode, out[mode])
         del DP, x, p, g, X, Mo
         torch.cuda.empty_cache()
@@ -866,6 +876,9 @@ def main():
     ap.add_argument("--dual", default=None, metavar="U,M",
                     help="fix the dual-form length bounds of the user and item plans instead of "
                          "timing the candidates (profiling runs)")
+    ap.add_argument("--grad-slices", type=int, default=None, metavar="S",
+                    help="fix the column slices of the M-block gradient's plan (0: none) "
+                         "instead of timing the candidates")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM traffic counters)")
     ap.add_argument("--gather-probe", action="store_true",
@@ -916,6 +929,12 @@ def main():
         bins[side] = tune.tune_dual(DP, side, Y, X_t, candidates=cands)
         log("length bins %s: %s" % (side, bins[side]))
         del X_t
+    # the M-block gradient's plan: cut at column slices of the user rows or not
+    X_t = torch.empty((P.n_m, DP.ld), dtype=torch.float32, device=ctx.torch_device)
+    gcands = (args.grad_slices,) if args.grad_slices is not None else tune.GRAD_SLICE_CANDIDATES
+    gslices = tune.tune_grad_slices(DP, DP.U(x_t), DP.M(x_t), X_t, candidates=gcands)
+    log("gradient column slices: %s" % gslices)
+    del X_t
     del x_t
     # Every decision of an iteration (line search, restart, safeguard) is
     # taken on the device, so the iterations are queued back to back with no
@@ -986,6 +1005,7 @@ def main():
         "roofline": roofline,
         "length_bins": {k: v["best"] for k, v in bins.items()},
         "length_bin_trials": {k: v["trials"] for k, v in bins.items()},
+        "grad_slices": gslices,
         "f": solver.f,
         "restarts": solver.restarts,
         "safeguards": solver.safeguards,

@@ -133,6 +133,25 @@ ALS_API int als_plan_info(const als_plan *plan, int64_t out[8]);
  * plan's chunks on the host and device (synchronises the device first);
  * results of every other call do not depend on the order.  Used by the tuner. */
 ALS_API int als_plan_set_dual(als_plan *plan, int64_t max_len);
+/* Plan of R for the gradient pass (Section V-C "Gradient Evaluation": the
+ * per-rating terms of a row summed over the row's ratings) with each row cut
+ * at n_slices column-slice boundaries, chosen so that every slice holds about
+ * nnz / n_slices ratings.  Every non-empty segment of a row is a piece of its
+ * own (segments longer than `chunk` are cut further, chunk = 0 as in
+ * als_plan_create), summed by the fixed-order split stage.  Pieces are laid
+ * out so that, with one workgroup per piece and workgroups handed to the
+ * device's 8 accelerator dies in turn, slice s runs on die s mod 8, slices
+ * s and s + 8 one after the other: each die then gathers rows of the other
+ * factor from one slice at a time, a table 8 / n_slices of the whole, which
+ * its own L2 can hold.  Slots of the layout that a slice does not fill are
+ * empty pieces.  Requires ascending column ids within every row (checked);
+ * copies R->indptr and R->indices to the host (synchronises the device).
+ * n_slices in [1, 4096].  Accepted as plan_R or plan_Rt by ncg_gradient
+ * only (ALS_E_INVAL elsewhere, and from als_plan_set_dual); results agree
+ * with those of an als_plan_create plan to rounding (another summation
+ * order), and are bitwise reproducible for a given plan. */
+ALS_API int als_plan_create_sliced(als_ctx *ctx, const als_csr *R, int64_t chunk, int64_t n_slices,
+                                   als_plan **out);
 
 /* ---------------------------------------------------------------- hot path */
 

@@ -53,6 +53,7 @@ _SIGS = {
     "als_plan_set_grid": (_i, [_vp, _i64, _i64]),
     "als_plan_info": (_i, [_vp, ctypes.POINTER(_i64)]),
     "als_plan_set_dual": (_i, [_vp, _i64]),
+    "als_plan_create_sliced": (_i, [_vp, _csrp, _i64, _i64, ctypes.POINTER(_vp)]),
     "als_sweep": (_i, [_vp, _vp, _csrp, _vp, _vp, _i, _i, _d, _i, _vp, _vp, _vp, _vp]),
     "als_sweep_mixed": (_i, [_vp, _vp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _vp, _vp]),
     "als_to_bf16": (_i, [_vp, _i64, _vp, _vp, _vp]),
@@ -158,6 +159,13 @@ def als_ctx_workspace_bytes(ctx) -> int:
 def als_plan_create(ctx, R: Csr, chunk: int = 0):
     out = _vp()
     _check("als_plan_create", load().als_plan_create(ctx, ctypes.byref(R), int(chunk), ctypes.byref(out)))
+    return out.value
+
+
+def als_plan_create_sliced(ctx, R: Csr, chunk: int, n_slices: int):
+    out = _vp()
+    _check("als_plan_create_sliced", load().als_plan_create_sliced(
+        ctx, ctypes.byref(R), int(chunk), int(n_slices), ctypes.byref(out)))
     return out.value
 
 

@@ -58,8 +58,14 @@ static bool csr_ok(const als_csr *R) {
     return true;
 }
 
-static bool plan_matches(const Plan *p, const als_csr *R) {
+// Any plan of R's shape (the gradient pass); plan_matches: one that is not
+// cut at column slices (every other call).
+static bool grad_plan_matches(const Plan *p, const als_csr *R) {
     return p && p->n_rows == R->n_rows && p->nnz == R->nnz;
+}
+
+static bool plan_matches(const Plan *p, const als_csr *R) {
+    return grad_plan_matches(p, R) && p->col_slices == 0;
 }
 
 static bool lambda_ok(double lambda) { return lambda >= 0.0 && isfinite(lambda); }
@@ -174,7 +180,7 @@ int als_plan_info(const als_plan *p, int64_t out[8]) {
 }
 
 int als_plan_set_dual(als_plan *p, int64_t max_len) {
-    if (!p || max_len < 0 || max_len > alsncg::kDualMaxLen) return ALS_E_INVAL;
+    if (!p || max_len < 0 || max_len > alsncg::kDualMaxLen || p->col_slices) return ALS_E_INVAL;
     max_len = std::min<int64_t>(max_len, p->chunk);  // dual rows are whole rows
     const size_t nc = p->h_row.size();
     auto is_dual = [&](size_t k) {
@@ -337,6 +343,184 @@ int als_plan_create(als_ctx *ctx, const als_csr *R, int64_t chunk, als_plan **ou
     return ALS_OK;
 }
 
+// Column slices of a sliced plan: at most this many.
+static constexpr int64_t kMaxColSlices = 4096;
+
+int als_plan_create_sliced(als_ctx *ctx, const als_csr *R, int64_t chunk, int64_t n_slices,
+                           als_plan **out) {
+    if (!out) return ALS_E_INVAL;
+    *out = nullptr;
+    if (!ctx || !csr_ok(R) || chunk < 0 || n_slices < 1 || n_slices > kMaxColSlices)
+        return ALS_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ALS_E_HIP;
+    const int64_t n = R->n_rows, nnz = R->nnz, n_cols = R->n_cols;
+    std::vector<int64_t> ip((size_t)n + 1);
+    std::vector<int32_t> ix((size_t)nnz);
+    if (hipDeviceSynchronize() != hipSuccess) return ALS_E_HIP;
+    if (hipMemcpy(ip.data(), R->indptr, ip.size() * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return ALS_E_HIP;
+    if (nnz > 0 &&
+        hipMemcpy(ix.data(), R->indices, ix.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return ALS_E_HIP;
+    if (ip[0] != 0 || ip[(size_t)n] != nnz) return ALS_E_INVAL;
+    // rows must hold ascending column ids: a slice is then one contiguous
+    // segment of every row
+    int64_t max_row = 0;
+    std::vector<int64_t> col_count((size_t)n_cols + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t b = ip[(size_t)i], e = ip[(size_t)i + 1];
+        if (e < b || e - b > n_cols) return ALS_E_INVAL;
+        max_row = std::max(max_row, e - b);
+        for (int64_t k = b; k < e; ++k) {
+            if (ix[(size_t)k] < 0 || ix[(size_t)k] >= n_cols) return ALS_E_INVAL;
+            if (k > b && ix[(size_t)k] <= ix[(size_t)k - 1]) return ALS_E_INVAL;
+            ++col_count[(size_t)ix[(size_t)k] + 1];
+        }
+    }
+    if (chunk == 0) {
+        const int64_t slots = (int64_t)ctx->num_cu * 8;
+        chunk = std::max<int64_t>(256, (nnz + slots - 1) / slots);
+        chunk = std::min<int64_t>(chunk, kMaxAutoChunk);
+        chunk = (chunk + 3) / 4 * 4;
+    }
+    chunk = std::min<int64_t>(chunk, INT32_MAX / 2);
+    // slice boundaries: columns [bound[s], bound[s + 1]) hold about nnz / S
+    // ratings each (prefix counts of the column ids)
+    const int64_t S = n_slices;
+    std::partial_sum(col_count.begin(), col_count.end(), col_count.begin());
+    std::vector<int64_t> bound((size_t)S + 1);
+    bound[0] = 0;
+    bound[(size_t)S] = n_cols;
+    for (int64_t s = 1; s < S; ++s) {
+        const int64_t target = (nnz * s + S - 1) / S;
+        bound[(size_t)s] =
+            std::lower_bound(col_count.begin(), col_count.end(), target) - col_count.begin();
+        bound[(size_t)s] = std::min(std::max(bound[(size_t)s], bound[(size_t)s - 1]), n_cols);
+    }
+    // pieces of every row: one per non-empty slice segment, segments longer
+    // than `chunk` cut further; a row of more than one piece is a split row
+    std::vector<std::vector<int64_t>> by_slice((size_t)S);  // piece ids per slice
+    std::vector<int32_t> crow, clen, cslot, srow, sslot0, snslot;
+    std::vector<int64_t> cbeg;
+    std::vector<int64_t> seg_s, seg_b, seg_e;
+    int64_t slots = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t b = ip[(size_t)i], e = ip[(size_t)i + 1];
+        seg_s.clear();
+        seg_b.clear();
+        seg_e.clear();
+        int64_t pieces = 0, p0 = b;
+        for (int64_t s = 0; s < S && p0 < e; ++s) {
+            const int64_t q =
+                std::lower_bound(ix.begin() + p0, ix.begin() + e, (int32_t)std::min<int64_t>(bound[(size_t)s + 1], INT32_MAX)) -
+                ix.begin();
+            if (q > p0) {
+                seg_s.push_back(s);
+                seg_b.push_back(p0);
+                seg_e.push_back(q);
+                const int64_t len = q - p0;
+                pieces += len <= chunk ? 1 : (len + chunk - 1) / chunk;
+            }
+            p0 = q;
+        }
+        if (pieces <= 1) {
+            // the whole row in one piece; an empty row (its gradient row is
+            // written as zeros) goes to slice i mod S
+            by_slice[(size_t)(pieces ? seg_s[0] : i % S)].push_back((int64_t)crow.size());
+            crow.push_back((int32_t)i);
+            cbeg.push_back(b);
+            clen.push_back((int32_t)(e - b));
+            cslot.push_back(-1);
+            continue;
+        }
+        const int64_t s0 = slots;
+        for (size_t t = 0; t < seg_s.size(); ++t) {
+            const int64_t len = seg_e[t] - seg_b[t];
+            const int64_t nck = len <= chunk ? 1 : (len + chunk - 1) / chunk;
+            const int64_t per = (len + nck - 1) / nck;
+            for (int64_t o = 0; o < len; o += per) {
+                by_slice[(size_t)seg_s[t]].push_back((int64_t)crow.size());
+                crow.push_back((int32_t)i);
+                cbeg.push_back(seg_b[t] + o);
+                clen.push_back((int32_t)std::min(per, len - o));
+                cslot.push_back((int32_t)(slots++));
+            }
+        }
+        srow.push_back((int32_t)i);
+        sslot0.push_back((int32_t)s0);
+        snslot.push_back((int32_t)(slots - s0));
+    }
+    if (slots >= INT32_MAX) return ALS_E_INVAL;
+    // launch order: slice s on die s mod kXcds, slices s and s + kXcds one
+    // after the other (phase s / kXcds); position kXcds k + x of a phase is
+    // the k-th longest piece of its slice, or an empty piece that writes
+    // zeros to a spare slot when the slice has fewer
+    std::vector<int32_t> crow2, clen2, cslot2;
+    std::vector<int64_t> cbeg2;
+    const int32_t spare = (int32_t)slots;
+    bool padded = false;
+    for (int64_t ph = 0; ph * kXcds < S; ++ph) {
+        size_t K = 0;
+        for (int64_t x = 0; x < kXcds && ph * kXcds + x < S; ++x) {
+            auto &v = by_slice[(size_t)(ph * kXcds + x)];
+            std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t c) { return clen[(size_t)a] > clen[(size_t)c]; });
+            K = std::max(K, v.size());
+        }
+        for (size_t k = 0; k < K; ++k)
+            for (int64_t x = 0; x < kXcds; ++x) {
+                const int64_t s = ph * kXcds + x;
+                if (s < S && k < by_slice[(size_t)s].size()) {
+                    const size_t c = (size_t)by_slice[(size_t)s][k];
+                    crow2.push_back(crow[c]);
+                    cbeg2.push_back(cbeg[c]);
+                    clen2.push_back(clen[c]);
+                    cslot2.push_back(cslot[c]);
+                } else {
+                    crow2.push_back(0);
+                    cbeg2.push_back(0);
+                    clen2.push_back(0);
+                    cslot2.push_back(spare);
+                    padded = true;
+                }
+            }
+    }
+    als_plan *p = new (std::nothrow) als_plan();
+    if (!p) return ALS_E_NOMEM;
+    p->n_rows = n;
+    p->nnz = nnz;
+    p->n_chunks = (int64_t)crow2.size();
+    p->n_split_rows = (int64_t)srow.size();
+    p->n_slots = slots + (padded ? 1 : 0);
+    p->chunk = chunk;
+    p->max_row = max_row;
+    p->col_slices = S;
+    int rc = upload(&p->chunk_row, crow2);
+    if (rc == ALS_OK) rc = upload(&p->chunk_begin, cbeg2);
+    if (rc == ALS_OK) rc = upload(&p->chunk_len, clen2);
+    if (rc == ALS_OK) rc = upload(&p->chunk_slot, cslot2);
+    if (rc == ALS_OK) rc = upload(&p->split_row, srow);
+    if (rc == ALS_OK) rc = upload(&p->split_slot0, sslot0);
+    if (rc == ALS_OK) rc = upload(&p->split_nslot, snslot);
+    if (rc == ALS_OK) {
+        std::vector<int32_t> slot_chunk((size_t)p->n_slots, 0);
+        for (size_t k = 0; k < cslot2.size(); ++k)
+            if (cslot2[k] >= 0) slot_chunk[(size_t)cslot2[k]] = (int32_t)k;
+        rc = upload(&p->slot_chunk, slot_chunk);
+    }
+    if (rc == ALS_OK) {
+        p->h_row = crow2;
+        p->h_len = clen2;
+        p->h_slot = cslot2;
+        p->h_beg = cbeg2;
+    }
+    if (rc != ALS_OK) {
+        als_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return ALS_OK;
+}
+
 int als_sweep(als_ctx *ctx, const als_plan *plan, const als_csr *R, const void *Y, void *X,
               int n_f, int ld, double lambda, als_dtype dt, const void *X_at, void *grad_out,
               int64_t *bad_row, void *stream) {
@@ -376,8 +560,8 @@ int als_to_bf16(als_ctx *ctx, int64_t n, const float *x, void *y, void *stream) 
 int ncg_gradient(als_ctx *ctx, const als_plan *plan_R, const als_csr *R, const als_plan *plan_Rt,
                  const als_csr *Rt, const void *U, const void *M, int n_f, int ld, double lambda,
                  als_dtype dt, void *gU, void *gM, double *out2, void *stream) {
-    if (!ctx || !csr_ok(R) || !csr_ok(Rt) || !plan_matches(plan_R, R) ||
-        !plan_matches(plan_Rt, Rt) || !U || !M || ld < n_f || !lambda_ok(lambda) ||
+    if (!ctx || !csr_ok(R) || !csr_ok(Rt) || !grad_plan_matches(plan_R, R) ||
+        !grad_plan_matches(plan_Rt, Rt) || !U || !M || ld < n_f || !lambda_ok(lambda) ||
         !dtype_ok(dt, n_f, false))
         return ALS_E_INVAL;
     if (R->n_rows != Rt->n_cols || R->n_cols != Rt->n_rows || R->nnz != Rt->nnz) return ALS_E_INVAL;

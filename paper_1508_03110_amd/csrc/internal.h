@@ -193,7 +193,15 @@ struct Plan {
     // host copies of the chunk arrays (in chunk order), kept to re-bin
     std::vector<int32_t> h_row, h_len, h_slot;
     std::vector<int64_t> h_beg;
+    // > 0: rows cut at column-slice boundaries (als_plan_create_sliced); such
+    // a plan serves the gradient pass only
+    int64_t col_slices = 0;
 };
+
+// Accelerator dies (XCDs) of the device, each with its own L2: the
+// workgroups of a one-dimensional launch are handed to them in turn, so
+// workgroup b runs on die b mod kXcds.
+constexpr int64_t kXcds = 8;
 
 // Largest dual system: kDualMaxBlocks tiles of 16 (rows of at most
 // 16 kDualMaxBlocks - 2 ratings: one slot for the right-hand side, one for

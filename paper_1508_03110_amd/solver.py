@@ -106,6 +106,17 @@ class DeviceCsr:
         L.als_plan_set_dual(self.plan, int(max_len))
         self.dual_max = int(max_len)
 
+    def set_grad_slices(self, n_slices: int, chunk: int = 0):
+        """Give the gradient pass its own plan with every row cut at n_slices
+        column slices (one slice per die of the device at a time, so that
+        the gathered rows of each slice stay in that die's L2); 0 drops it."""
+        if getattr(self, "grad_plan", None):
+            L.als_plan_destroy(self.grad_plan)
+            self.grad_plan = None
+        self.grad_slices = int(n_slices)
+        if n_slices > 0:
+            self.grad_plan = L.als_plan_create_sliced(self.ctx.handle, self.csr, int(chunk), int(n_slices))
+
     def set_grid(self, grid: int, grid_pass: int = 0):
         """Persistent grids of the half-sweep and of the streaming passes (0: one
         workgroup per chunk)."""
@@ -116,6 +127,9 @@ class DeviceCsr:
         if getattr(self, "plan", None):
             L.als_plan_destroy(self.plan)
             self.plan = None
+        if getattr(self, "grad_plan", None):
+            L.als_plan_destroy(self.grad_plan)
+            self.grad_plan = None
 
     def __del__(self):
         try:
@@ -179,7 +193,8 @@ class DeviceProblem:
         L.als_to_bf16(self.ctx.handle, X32.numel(), X32, X16)
 
     def gradient(self, U, M, gU=None, gM=None, out2=None):
-        L.ncg_gradient(self.ctx.handle, self.R.plan, self.R.csr, self.Rt.plan, self.Rt.csr, U, M,
+        L.ncg_gradient(self.ctx.handle, getattr(self.R, "grad_plan", None) or self.R.plan, self.R.csr,
+                       getattr(self.Rt, "grad_plan", None) or self.Rt.plan, self.Rt.csr, U, M,
                        self.n_f, self.ld, self.lam, self.dt, gU, gM, out2)
 
     def coeffs(self, U, M, pU, pM, out):

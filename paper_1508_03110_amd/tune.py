@@ -12,10 +12,13 @@ most `dual_max` ratings take the dual form (an n_i x n_i system, one kernel
 instance per 16-wide tile count), the rest the n_f x n_f form; candidates
 0 (off) and 16 b - 2 for b = 1 .. 6 tiles.  Last it picks the persistent
 grid of the orientation's streaming pass (coefficients for R, gradient for
-R^T), whose per-chunk work is small enough for workgroup dispatch to matter.
+R^T), whose per-chunk work is small enough for workgroup dispatch to matter,
+and whether the M-block gradient takes a plan of R^T cut at column slices
+(one slice of the user rows per die of the device at a time, so that each
+die's L2 holds the rows it gathers).
 Results do not depend on the chunk or the grids (every chunk reduces into
-its own slot in a fixed order), only time does; the dual form reaches the
-same per-row solution by a different rounding path.
+its own slot in a fixed order), only time does; the dual form and the
+column slices reach the same result by a different rounding path.
 """
 from __future__ import annotations
 
@@ -55,6 +58,23 @@ def tune_dual(DP, side: str, Y, X, reps: int = 3, candidates=DUAL_CANDIDATES) ->
                        "ms": round(_best_ms(lambda: DP.sweep(side, Y, X), reps), 4)})
     best = min(trials, key=lambda t: t["ms"])
     A.set_dual(best["dual_max"])
+    return {"best": best, "trials": trials}
+
+
+GRAD_SLICE_CANDIDATES = (0, 8)
+SLICE_TABLE_MAX = 256 << 20  # bytes of gathered rows up to which slices are tried
+
+
+def tune_grad_slices(DP, U, M, X, reps: int = 3, candidates=GRAD_SLICE_CANDIDATES) -> dict:
+    """Pick the column slices of the M-block gradient's plan (0: the plan of
+    the half-sweep) by timing that pass (X: output rows of M's shape);
+    leaves the best one set."""
+    trials = []
+    for n in candidates:
+        DP.Rt.set_grad_slices(n)
+        trials.append({"slices": n, "ms": round(_best_ms(lambda: DP.gradient(U, M, None, X, None), reps), 4)})
+    best = min(trials, key=lambda t: t["ms"])
+    DP.Rt.set_grad_slices(best["slices"])
     return {"best": best, "trials": trials}
 
 
@@ -98,6 +118,21 @@ def tune(DP, x, reps: int = 2, chunk_factors=(1.0, 0.25), grids_per_cu=(0, 4, 8,
             ptrials.append({"grid_pass": gpc * n_cu, "ms": round(_best_ms(run, reps), 4)})
         pbest = min(ptrials, key=lambda t: t["ms"])
         A.set_grid(best["grid"], pbest["grid_pass"])
+        # slices are tried only while the gathered user rows fit the device's
+        # 256 MB last-level cache: beyond it one die's slice is far larger
+        # than its L2 and the extra pieces are not expected to pay
+        table = DP.n_u * DP.ld * DP.zeros(1).element_size()
+        if side == "M" and table <= SLICE_TABLE_MAX:
+            sl = tune_grad_slices(DP, U, M, X, reps=reps)
+            if sl["best"]["slices"] and sl["best"]["ms"] < pbest["ms"]:
+                pbest = {"grid_pass": pbest["grid_pass"], "ms": sl["best"]["ms"]}
+                best = dict(best, grad_slices=sl["best"]["slices"])
+            else:
+                DP.Rt.set_grad_slices(0)
+                best = dict(best, grad_slices=0)
+            ptrials = ptrials + [dict(t, grid_pass=0) for t in sl["trials"] if t["slices"]]
+        elif side == "M":
+            best = dict(best, grad_slices=0)
         out[side] = {"best": dict(best, grid_pass=pbest["grid_pass"], pass_ms=pbest["ms"]),
                      "default_ms": trials[0]["ms"], "default_pass_ms": ptrials[0]["ms"],
                      "trials": trials, "dual_trials": dual["trials"], "pass_trials": ptrials,
