@@ -69,17 +69,19 @@ def kernel_source_hash():
     return m.hexdigest()[:16]
 
 
-def profiled_traffic(dual_max):
+def profiled_traffic(dual_max, split_copy=0):
     """HBM bytes per U half-sweep (all its launches) from the committed
-    rocprofv3 counter summary for this length bound, or None when the kernel
-    sources changed since it was taken or the bound was not profiled."""
+    rocprofv3 counter summary for this length bound and split-copy choice,
+    or None when the kernel sources changed since it was taken or that
+    configuration was not profiled."""
     path = os.path.join(ROOT, "profiles", "sweep_chunks_f32_nf100_ml20m_shape.md")
     try:
         for line in open(path):
             line = line.strip()
             if line.startswith("TRAFFIC "):
                 d = json.loads(line[len("TRAFFIC "):])
-                if d.get("source_hash") == kernel_source_hash() and d.get("dual_max") == dual_max:
+                if (d.get("source_hash") == kernel_source_hash() and d.get("dual_max") == dual_max
+                        and d.get("split_copy", 0) == split_copy):
                     return int(d["bytes"])
     except OSError:
         pass
@@ -725,6 +727,8 @@ def compact(res, full_path):
         out["dual_max"] = {k: v["dual_max"] for k, v in res["length_bins"].items()}
     if "grad_slices" in res:
         out["grad_slices"] = res["grad_slices"]["best"]["slices"]
+    if "split_copy" in res:
+        out["split_copy"] = res["split_copy"]
     tt = res.get("time_to_tol")
     if tt:
         sm = {"f_gap_tol": tt["f_gap_tol"], "gnorm_over_N_tol": tt["gnorm_over_N_tol"]}
@@ -876,6 +880,9 @@ def main():
     ap.add_argument("--dual", default=None, metavar="U,M",
                     help="fix the dual-form length bounds of the user and item plans instead of "
                          "timing the candidates (profiling runs)")
+    ap.add_argument("--split-copy", default=None, metavar="U,M",
+                    help="fix whether the user and item half-sweeps gather a split copy of the "
+                         "fixed side (1/0) instead of timing both")
     ap.add_argument("--grad-slices", type=int, default=None, metavar="S",
                     help="fix the column slices of the M-block gradient's plan (0: none) "
                          "instead of timing the candidates")
@@ -921,13 +928,19 @@ def main():
     # length bins of the half-sweeps: the dual-form bound of each plan, by timing
     from paper_1508_03110_amd import tune
     x_t = DP.pack(U0, M0)
-    bins = {}
+    bins, splits = {}, {}
     fixed = [int(v) for v in args.dual.split(",")] if args.dual else None
     for k, (side, Y, n) in enumerate((("U", DP.M(x_t), P.n_u), ("M", DP.U(x_t), P.n_m))):
         X_t = torch.empty((n, DP.ld), dtype=torch.float32, device=ctx.torch_device)
         cands = (fixed[k],) if fixed else tune.DUAL_CANDIDATES
         bins[side] = tune.tune_dual(DP, side, Y, X_t, candidates=cands)
         log("length bins %s: %s" % (side, bins[side]))
+        if args.split_copy is not None:
+            (DP.R if side == "U" else DP.Rt).set_split_copy(int(args.split_copy.split(",")[k]))
+            splits[side] = {"best": {"split_copy": int(args.split_copy.split(",")[k])}, "trials": []}
+        else:
+            splits[side] = tune.tune_split_copy(DP, side, Y, X_t)
+        log("split copy %s: %s" % (side, splits[side]))
         del X_t
     # the M-block gradient's plan: cut at column slices of the user rows or not
     X_t = torch.empty((P.n_m, DP.ld), dtype=torch.float32, device=ctx.torch_device)
@@ -970,7 +983,7 @@ def main():
                 "kernel": "U half-sweep: sweep_chunks_kernel<float,7> + sweep_dual_kernel bins",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": profiled_traffic(bins["U"]["best"]["dual_max"]),
+                "traffic": profiled_traffic(bins["U"]["best"]["dual_max"], splits["U"]["best"]["split_copy"]),
                 "flops_per_launch": fU, "launch_ms": round(phases["sweep_U"], 4),
                 "eq3_flops_per_launch": fU3,
                 "frac_eq3_count": round(fU3 / tU / 1e12 / PEAK_FP32_TFLOPS, 4),
@@ -1006,6 +1019,8 @@ def main():
         "length_bins": {k: v["best"] for k, v in bins.items()},
         "length_bin_trials": {k: v["trials"] for k, v in bins.items()},
         "grad_slices": gslices,
+        "split_copy": {k: v["best"]["split_copy"] for k, v in splits.items()},
+        "split_copy_trials": {k: v["trials"] for k, v in splits.items()},
         "f": solver.f,
         "restarts": solver.restarts,
         "safeguards": solver.safeguards,

@@ -133,6 +133,19 @@ ALS_API int als_plan_info(const als_plan *plan, int64_t out[8]);
  * plan's chunks on the host and device (synchronises the device first);
  * results of every other call do not depend on the order.  Used by the tuner. */
 ALS_API int als_plan_set_dual(als_plan *plan, int64_t max_len);
+/* FP32 half-sweep of this plan (Eq. (3)/(4)) over a split copy of the fixed
+ * side: als_sweep first writes, once per call, the two-term FP16 split of
+ * every row of Y (the values its Gram loop otherwise forms for every
+ * gathered rating) into a context-owned device buffer (grown as needed,
+ * like the workspace; calls on one context that overlap on different
+ * streams race on it), and the Gram loop gathers the split rows: fewer
+ * instructions per rating, rows of 64 * ceil(NB / 4) * 4 bytes with
+ * NB = ceil((n_f + 1) / 16) instead of 4 ld.  Results are bitwise the same
+ * either way.  mode 1: on; 0: off; -1 (default): on when the split rows are
+ * no wider than the factor rows.  Not used for the dual-form bins, for FP64,
+ * for fold-in or the server, or when the copy would exceed 4 GiB.  Used by
+ * the tuner. */
+ALS_API int als_plan_set_split_copy(als_plan *plan, int mode);
 /* Plan of R for the gradient pass (Section V-C "Gradient Evaluation": the
  * per-rating terms of a row summed over the row's ratings) with each row cut
  * at n_slices column-slice boundaries, chosen so that every slice holds about

@@ -54,6 +54,7 @@ _SIGS = {
     "als_plan_info": (_i, [_vp, ctypes.POINTER(_i64)]),
     "als_plan_set_dual": (_i, [_vp, _i64]),
     "als_plan_create_sliced": (_i, [_vp, _csrp, _i64, _i64, ctypes.POINTER(_vp)]),
+    "als_plan_set_split_copy": (_i, [_vp, _i]),
     "als_sweep": (_i, [_vp, _vp, _csrp, _vp, _vp, _i, _i, _d, _i, _vp, _vp, _vp, _vp]),
     "als_sweep_mixed": (_i, [_vp, _vp, _csrp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _vp, _vp]),
     "als_to_bf16": (_i, [_vp, _i64, _vp, _vp, _vp]),
@@ -167,6 +168,10 @@ def als_plan_create_sliced(ctx, R: Csr, chunk: int, n_slices: int):
     _check("als_plan_create_sliced", load().als_plan_create_sliced(
         ctx, ctypes.byref(R), int(chunk), int(n_slices), ctypes.byref(out)))
     return out.value
+
+
+def als_plan_set_split_copy(plan, mode):
+    return _check("als_plan_set_split_copy", load().als_plan_set_split_copy(plan, int(mode)))
 
 
 def als_plan_destroy(plan):

@@ -43,6 +43,28 @@ void *Ctx::workspace(size_t bytes, hipStream_t stream, int *err) {
     return ws;
 }
 
+void *Ctx::split_buffer(size_t bytes, hipStream_t stream, int *err) {
+    if (bytes == 0) bytes = 256;
+    if (bytes <= ysplit_bytes) return ysplit;
+    if (ysplit) {
+        if (hipStreamSynchronize(stream) != hipSuccess) {
+            *err = ALS_E_HIP;
+            return nullptr;
+        }
+        (void)hipFree(ysplit);
+        ysplit = nullptr;
+        ysplit_bytes = 0;
+    }
+    const size_t want = align_up(bytes, 1 << 20);
+    if (hipMalloc(&ysplit, want) != hipSuccess) {
+        ysplit = nullptr;
+        *err = ALS_E_NOMEM;
+        return nullptr;
+    }
+    ysplit_bytes = want;
+    return ysplit;
+}
+
 static bool dtype_ok(als_dtype dt, int n_f, bool sweep) {
     if (n_f < 1) return false;
     if (dt == ALS_F32) return sweep ? n_f <= 143 : n_f <= 144;
@@ -144,6 +166,7 @@ void als_ctx_destroy(als_ctx *ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->ybits) (void)hipFree(ctx->ybits);
+    if (ctx->ysplit) (void)hipFree(ctx->ysplit);
     delete ctx;
 }
 
@@ -163,6 +186,12 @@ int als_plan_set_grid(als_plan *p, int64_t sweep_grid, int64_t pass_grid) {
         return ALS_E_INVAL;
     p->grid = sweep_grid;
     p->grid_pass = pass_grid;
+    return ALS_OK;
+}
+
+int als_plan_set_split_copy(als_plan *p, int mode) {
+    if (!p || mode < -1 || mode > 1 || p->col_slices) return ALS_E_INVAL;
+    p->split_copy = mode;
     return ALS_OK;
 }
 

@@ -196,6 +196,9 @@ struct Plan {
     // > 0: rows cut at column-slice boundaries (als_plan_create_sliced); such
     // a plan serves the gradient pass only
     int64_t col_slices = 0;
+    // FP32 half-sweep over a split copy of the fixed side: 1 on, 0 off, -1
+    // (default) on when the copy's rows are no wider than the factor rows
+    int split_copy = -1;
 };
 
 // Accelerator dies (XCDs) of the device, each with its own L2: the
@@ -222,8 +225,14 @@ struct Ctx {
     // |Y|; kAbsMaxWords in all), rewritten before every FP32 half-sweep on
     // this context
     unsigned *ybits = nullptr;
+    // FP16 split copy of the fixed side of the FP32 half-sweep (rewritten by
+    // every planned FP32 half-sweep on this context) and its size
+    void *ysplit = nullptr;
+    size_t ysplit_bytes = 0;
     // Returns workspace of at least `bytes` (grows; synchronises before freeing).
     void *workspace(size_t bytes, hipStream_t stream, int *err);
+    // The split copy's buffer, grown the same way.
+    void *split_buffer(size_t bytes, hipStream_t stream, int *err);
 };
 
 }  // namespace alsncg

@@ -377,6 +377,184 @@ __device__ __forceinline__ void gram_split(Mfma<float>::acc4 (&A)[Tri<NB>::NT],
             }
 }
 
+// ---------------------------------------------------------------- split copy of the fixed side
+//
+// A planned FP32 half-sweep splits the fixed side once per call instead of
+// once per gathered rating.  Row j of the copy holds, for lane c of a 16-lane
+// group and block a < NB, the dword (h, m) of x = 2^sy Y[j][col(16 a + c)]
+// (h = fp16(x) in the low half, m = fp16(x - h) in the high half: the values
+// the split in the Gram loop forms), and zero for slots at or past n_f.  A
+// lane's part is LW dwords (NB rounded up to whole 16-byte vectors), a row
+// 16 LW dwords; one more row of zeros (row n) stands in for the positions
+// past the end of a chunk.
+template <int NB> struct SplitRow {
+    static constexpr int LW = (NB + 3) / 4 * 4;
+    static constexpr int W = 16 * LW;
+};
+
+template <int NB>
+__global__ __launch_bounds__(256) void presplit_kernel(const float *__restrict__ Y, int64_t n,
+                                                       int n_f, int ld,
+                                                       const unsigned *__restrict__ ybits,
+                                                       unsigned *__restrict__ Yp) {
+    typedef SplitRow<NB> SR;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (n + 1) * 16) return;
+    const int64_t j = t >> 4;
+    const int c = (int)(t & 15);
+    const float Sy = exp2i(split_shift(*ybits, 0u));
+    const float *row = Y + j * ld;
+    unsigned d[SR::LW];
+#pragma unroll
+    for (int a = 0; a < SR::LW; ++a) {
+        const int k = 16 * a + c;
+        const float x = (j < n && a < NB && k < n_f) ? row[Slots<NB>::col(k)] * Sy : 0.0f;
+        unsigned hi, lo;
+        split2(x, 0.0f, hi, lo);
+        d[a] = (hi & 0xffffu) | (lo << 16);
+    }
+    u32x4_t *dst = (u32x4_t *)(Yp + j * SR::W + c * SR::LW);
+#pragma unroll
+    for (int q = 0; q < SR::LW / 4; ++q) dst[q] = u32x4_t{d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]};
+}
+
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x3_t __attribute__((ext_vector_type(3)));
+
+// The NB dwords of a lane's part of a row at byte offset `off` of Yp (the
+// copy is smaller than 4 GiB: a 32-bit offset from a uniform base).
+template <int NB>
+__device__ __forceinline__ void gather_split(unsigned (&d)[NB], const unsigned *__restrict__ Yp,
+                                             unsigned off) {
+    const unsigned *p = (const unsigned *)((const char *)Yp + off);
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) {
+        const u32x4_t v = *(const u32x4_t *)(p + 4 * q);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[4 * q + e] = v[e];
+    }
+    constexpr int o = NB / 4 * 4;
+    if constexpr (NB % 4 == 3) {
+        const u32x3_t v = *(const u32x3_t *)(p + o);
+        d[o] = v[0];
+        d[o + 1] = v[1];
+        d[o + 2] = v[2];
+    } else if constexpr (NB % 4 == 2) {
+        const u32x2_t v = *(const u32x2_t *)(p + o);
+        d[o] = v[0];
+        d[o + 1] = v[1];
+    } else if constexpr (NB % 4 == 1) {
+        d[o] = p[o];
+    }
+}
+
+// gram_split over the split copy Yp (n_y rows and the zero row n_y): the
+// same lanes, scales, MFMAs and unscaling, with the operands of a group of 32
+// ratings formed from the 8 gathered rows of a lane by byte permutes (the h
+// halves of ratings 2 i and 2 i + 1 at one slot into one dword, the m halves
+// into another) instead of three instructions of split per value.  The
+// rating slot (lane n_f - 16 (NB - 1) of the last block, zero in the copy) is
+// split in the loop with the chunk's scale.  Positions past the end of the
+// chunk gather the zero row and a zero rating.  Yields the same Gram, bit for
+// bit, as gram_split.
+template <int NB>
+__device__ __forceinline__ void gram_split_pre(Mfma<float>::acc4 (&A)[Tri<NB>::NT],
+                                               const int32_t *__restrict__ idx,
+                                               const float *__restrict__ val, int64_t b, int64_t e,
+                                               const unsigned *__restrict__ Yp, int n_y, int n_f,
+                                               unsigned ybits, int g, int c) {
+    typedef Tri<NB> TR;
+    typedef SplitRow<NB> SR;
+    if (b >= e) return;
+    const int last = (int)(e - 1 - b);
+    const int ng = (last >> 5) + 1;
+    const int32_t *ix = idx + b;
+    const float *vx = val + b;
+    auto at = [&](int t, int k) { return 32 * t + 8 * g + k; };
+    auto pos = [&](int t, int k) { return (unsigned)min(at(t, k), last); };
+    const unsigned lane_off = (unsigned)c * SR::LW * 4u;
+    // byte offset of the gathered part of position (t, k) holding id j
+    auto offset = [&](int t, int k, int j) {
+        return (unsigned)(at(t, k) <= last ? j : n_y) * (unsigned)(SR::W * 4) + lane_off;
+    };
+    unsigned raw[8][NB];
+    float rv[8];
+    int jq[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) jq[k] = ix[pos(0, k)];
+    float rmax = abs_max_step(vx, 0, last, 16 * g + c);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        gather_split<NB>(raw[k], Yp, offset(0, k, jq[k]));
+        rv[k] = vx[pos(0, k)];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) jq[k] = ix[pos(1, k)];
+    for (int p0 = 16 * kWave; p0 <= last; p0 += 16 * kWave)
+        rmax = fmaxf(rmax, abs_max_step(vx, p0, last, 16 * g + c));
+    const int sy = split_shift(ybits, 0u);
+    const int sr = split_shift(0u, __float_as_uint(wave_max(rmax)));
+    const int caug = n_f - 16 * (NB - 1);  // lane of slot n_f in the last block
+    const bool rlane = c == caug;
+    const float Sr = exp2i(sr);
+    for (int t = 0; t < ng; ++t) {
+        u32x4_t hp[NB], lp[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                hp[a][i] = __builtin_amdgcn_perm(raw[2 * i + 1][a], raw[2 * i][a], 0x05040100u);
+                lp[a][i] = __builtin_amdgcn_perm(raw[2 * i + 1][a], raw[2 * i][a], 0x07060302u);
+            }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float r0 = at(t, 2 * i) <= last ? rv[2 * i] : 0.0f;
+            const float r1 = at(t, 2 * i + 1) <= last ? rv[2 * i + 1] : 0.0f;
+            unsigned rh, rl;
+            split2(r0 * Sr, r1 * Sr, rh, rl);
+            hp[NB - 1][i] = rlane ? rh : hp[NB - 1][i];
+            lp[NB - 1][i] = rlane ? rl : lp[NB - 1][i];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            gather_split<NB>(raw[k], Yp, offset(t + 1, k, jq[k]));
+            rv[k] = vx[pos(t + 1, k)];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb) A[TR::id(a, bb)] = mma_f16(hp[a], hp[bb], A[TR::id(a, bb)]);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb) A[TR::id(a, bb)] = mma_f16(hp[a], lp[bb], A[TR::id(a, bb)]);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int bb = a; bb < NB; ++bb) A[TR::id(a, bb)] = mma_f16(lp[a], hp[bb], A[TR::id(a, bb)]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) jq[k] = ix[pos(t + 2, k)];
+    }
+    const float Fyy = exp2i(-2 * sy), Fyr = exp2i(-sy - sr), Frr = exp2i(-2 * sr);
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int bb = a; bb < NB; ++bb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float f = Fyy;
+                if (bb == NB - 1) {
+                    const bool rrow = a == NB - 1 && Mfma<float>::row(g, r) == caug;
+                    const bool rcol = c == caug;
+                    f = rrow ? (rcol ? Frr : Fyr) : (rcol ? Fyr : Fyy);
+                }
+                A[TR::id(a, bb)][r] *= f;
+            }
+}
+
 // Regularise, optionally form the gradient 2 (A x_in - v), factorise, solve
 // and store one row.  `sm` is Shared<T, NB>::size elements of LDS.
 template <typename T, int NB, bool WS = false>
@@ -486,10 +664,11 @@ template <typename T, int NB> struct Occ {
 
 // One chunk: Gram of its ratings, then either the partial tiles (split row)
 // or the row solve.
-template <typename T, int NB, bool VEC>
+template <typename T, int NB, bool VEC, bool PRE>
 __device__ __forceinline__ void sweep_chunk(
     int64_t q, const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ Y, const unsigned *__restrict__ ybits,
+    const unsigned *__restrict__ Yp, int n_y,
     T *__restrict__ X, int n_f, int ld,
     T lambda, const int32_t *__restrict__ chunk_row, const int64_t *__restrict__ chunk_begin,
     const int32_t *__restrict__ chunk_len, const int32_t *__restrict__ chunk_slot,
@@ -515,7 +694,9 @@ __device__ __forceinline__ void sweep_chunk(
     acc4 A[TR::NT];
 #pragma unroll
     for (int t = 0; t < TR::NT; ++t) A[t] = acc4{T(0), T(0), T(0), T(0)};
-    if constexpr (sizeof(T) == 4)
+    if constexpr (sizeof(T) == 4 && PRE)
+        gram_split_pre<NB>(A, idx, val, b, b + len, Yp, n_y, n_f, *ybits, g, c);
+    else if constexpr (sizeof(T) == 4)
         gram_split<NB, VEC>(A, idx, val, b, b + len, Y, ld, n_f, *ybits, g, c);
     else
         gram_accumulate<T, NB, VEC>(A, idx, val, b, b + len, Y, ld, n_f, g, c);
@@ -534,10 +715,12 @@ __device__ __forceinline__ void sweep_chunk(
 // striding over the chunks (PERSIST = true; chunks are ordered longest
 // first, so the stride deals them out like a greedy schedule).
 // chunk_row == nullptr: chunk q is row q in full (fold-in and unplanned use).
-template <typename T, int NB, bool PERSIST, bool VEC>
+// PRE (FP32): the Gram reads the split copy Yp of Y instead of Y.
+template <typename T, int NB, bool PERSIST, bool VEC, bool PRE = false>
 __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     const int64_t *__restrict__ indptr, const int32_t *__restrict__ idx,
     const float *__restrict__ val, const T *__restrict__ Y, const unsigned *__restrict__ ybits,
+    const unsigned *__restrict__ Yp, int n_y,
     T *__restrict__ X, int n_f, int ld,
     T lambda, int64_t n_chunks, const int32_t *__restrict__ chunk_row,
     const int64_t *__restrict__ chunk_begin, const int32_t *__restrict__ chunk_len,
@@ -547,13 +730,13 @@ __global__ __launch_bounds__(64, (Occ<T, NB>::waves)) void sweep_chunks_kernel(
     __shared__ T sm[Shared<T, NB>::size];
     if constexpr (PERSIST) {
         for (int64_t q = blockIdx.x; q < n_chunks; q += gridDim.x)
-            sweep_chunk<T, NB, VEC>(q, indptr, idx, val, Y, ybits, X, n_f, ld, lambda, chunk_row,
+            sweep_chunk<T, NB, VEC, PRE>(q, indptr, idx, val, Y, ybits, Yp, n_y, X, n_f, ld, lambda, chunk_row,
                                     chunk_begin, chunk_len, chunk_slot, partial, X_at, grad_out,
                                     bad_row, status, empty_status, sm);
     } else {
         const int64_t q = blockIdx.x;
         if (q >= n_chunks) return;
-        sweep_chunk<T, NB, VEC>(q, indptr, idx, val, Y, ybits, X, n_f, ld, lambda, chunk_row,
+        sweep_chunk<T, NB, VEC, PRE>(q, indptr, idx, val, Y, ybits, Yp, n_y, X, n_f, ld, lambda, chunk_row,
                                 chunk_begin, chunk_len, chunk_slot, partial, X_at, grad_out,
                                 bad_row, status, empty_status, sm);
     }
@@ -667,7 +850,8 @@ int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, const 
     if (!plan) {
         if (n_rows_unplanned > 0)
             hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)n_rows_unplanned),
-                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, ybits, X,
+                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, ybits,
+                               (const unsigned *)nullptr, 0, X,
                                n_f, ld, lambda, n_rows_unplanned, nullptr, nullptr, nullptr,
                                nullptr, (acc4 *)nullptr, X_at, grad_out, bad_row, status,
                                empty_status);
@@ -683,21 +867,46 @@ int run_sweep_v(Ctx *ctx, const Plan *plan, const als_csr *R, const T *Y, const 
     // kernels; with lambda = 0 every row keeps the n_f x n_f form
     const bool dual = plan->n_dual > 0 && lambda > T(0) && !status;
     const int64_t n_main = dual ? plan->n_chunks - plan->n_dual : plan->n_chunks;
-    if (n_main > 0) {
-        if (plan->grid > 0)
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, true, VEC>),
-                               dim3((unsigned)std::min<int64_t>(plan->grid, n_main)),
-                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, ybits, X,
-                               n_f, ld, lambda, n_main, plan->chunk_row, plan->chunk_begin,
-                               plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
-                               status, empty_status);
-        else
-            hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, false, VEC>), dim3((unsigned)n_main),
-                               dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, ybits, X,
-                               n_f, ld, lambda, n_main, plan->chunk_row, plan->chunk_begin,
-                               plan->chunk_len, plan->chunk_slot, partial, X_at, grad_out, bad_row,
-                               status, empty_status);
+    // FP32 with a context: split the fixed side once into the context's copy
+    const unsigned *Yp = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        const size_t bytes = (size_t)(R->n_cols + 1) * SplitRow<NB>::W * sizeof(unsigned);
+        const bool want = plan->split_copy > 0 || (plan->split_copy < 0 && SplitRow<NB>::W <= ld);
+        if (want && ctx && n_main > 0 && bytes <= (size_t(1) << 32)) {
+            int err = ALS_OK;
+            unsigned *cp = (unsigned *)ctx->split_buffer(bytes, s, &err);
+            if (!cp) return err;
+            const int64_t nt = (R->n_cols + 1) * 16;
+            hipLaunchKernelGGL((presplit_kernel<NB>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
+                               s, (const float *)Y, R->n_cols, n_f, ld, ybits, cp);
+            Yp = cp;
+        }
     }
+#define ALS_MAIN(P, V, PR)                                                                         \
+    hipLaunchKernelGGL((sweep_chunks_kernel<T, NB, P, V, PR>),                                     \
+                       dim3((unsigned)(P ? std::min<int64_t>(plan->grid, n_main) : n_main)),        \
+                       dim3(kWave), 0, s, R->indptr, R->indices, R->values, Y, ybits, Yp,          \
+                       (int)R->n_cols, X, n_f,                                                     \
+                       ld, lambda, n_main, plan->chunk_row, plan->chunk_begin, plan->chunk_len,     \
+                       plan->chunk_slot, partial, X_at, grad_out, bad_row, status, empty_status)
+    bool launched = false;
+    if constexpr (sizeof(T) == 4) {
+        if (n_main > 0 && Yp) {
+            if (plan->grid > 0)
+                ALS_MAIN(true, false, true);
+            else
+                ALS_MAIN(false, false, true);
+            launched = true;
+        }
+    }
+    if (n_main > 0 && !launched) {
+        if (plan->grid > 0) {
+            ALS_MAIN(true, VEC, false);
+        } else {
+            ALS_MAIN(false, VEC, false);
+        }
+    }
+#undef ALS_MAIN
     if (dual) {
         const int rc = launch_sweep_dual(plan, R, Y, X, n_f, ld, (double)lambda, Mfma<T>::kDtype,
                                          X_at, grad_out, bad_row, s);

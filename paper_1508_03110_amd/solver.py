@@ -99,12 +99,20 @@ class DeviceCsr:
         self.set_grid(grid, grid_pass)
         if getattr(self, "dual_max", 0):
             L.als_plan_set_dual(self.plan, self.dual_max)
+        if getattr(self, "split_copy", -1) != -1:
+            L.als_plan_set_split_copy(self.plan, self.split_copy)
 
     def set_dual(self, max_len: int):
         """Solve rows of 1..max_len ratings (max_len <= 94) in the dual form
         of the half-sweep (an n_i x n_i system); 0 turns it off."""
         L.als_plan_set_dual(self.plan, int(max_len))
         self.dual_max = int(max_len)
+
+    def set_split_copy(self, mode: int):
+        """FP32 half-sweep over a split copy of the fixed side: 1 on, 0 off,
+        -1 on when its rows are no wider than the factor rows (default)."""
+        L.als_plan_set_split_copy(self.plan, int(mode))
+        self.split_copy = int(mode)
 
     def set_grad_slices(self, n_slices: int, chunk: int = 0):
         """Give the gradient pass its own plan with every row cut at n_slices

@@ -10,7 +10,8 @@ both algorithms) over a small grid of launch shapes and keeps the fastest:
 With that plan it then picks the length bins of the half-sweep: rows of at
 most `dual_max` ratings take the dual form (an n_i x n_i system, one kernel
 instance per 16-wide tile count), the rest the n_f x n_f form; candidates
-0 (off) and 16 b - 2 for b = 1 .. 6 tiles.  Last it picks the persistent
+0 (off) and 16 b - 2 for b = 1 .. 6 tiles; and, in FP32, whether the
+n_f x n_f form gathers a split copy of the fixed side.  Last it picks the persistent
 grid of the orientation's streaming pass (coefficients for R, gradient for
 R^T), whose per-chunk work is small enough for workgroup dispatch to matter,
 and whether the M-block gradient takes a plan of R^T cut at column slices
@@ -61,6 +62,20 @@ def tune_dual(DP, side: str, Y, X, reps: int = 3, candidates=DUAL_CANDIDATES) ->
     return {"best": best, "trials": trials}
 
 
+def tune_split_copy(DP, side: str, Y, X, reps: int = 3) -> dict:
+    """FP32: time one orientation's half-sweep with and without the split
+    copy of the fixed side (fewer instructions per rating against wider
+    gathered rows); leaves the faster one set."""
+    A = DP.R if side == "U" else DP.Rt
+    trials = []
+    for mode in (0, 1):
+        A.set_split_copy(mode)
+        trials.append({"split_copy": mode, "ms": round(_best_ms(lambda: DP.sweep(side, Y, X), reps), 4)})
+    best = min(trials, key=lambda t: t["ms"])
+    A.set_split_copy(best["split_copy"])
+    return {"best": best, "trials": trials}
+
+
 GRAD_SLICE_CANDIDATES = (0, 8)
 SLICE_TABLE_MAX = 256 << 20  # bytes of gathered rows up to which slices are tried
 
@@ -108,6 +123,9 @@ def tune(DP, x, reps: int = 2, chunk_factors=(1.0, 0.25), grids_per_cu=(0, 4, 8,
         A.replan(best["chunk"], best["grid"], 0)
         dual = tune_dual(DP, side, Y, X, reps=reps)
         best = dict(best, dual_max=dual["best"]["dual_max"], dual_ms=dual["best"]["ms"])
+        if DP.dtype == torch.float32:
+            sc = tune_split_copy(DP, side, Y, X, reps=reps)
+            best = dict(best, split_copy=sc["best"]["split_copy"], split_copy_ms=sc["best"]["ms"])
         if side == "U":  # the coefficient pass runs over R
             run = lambda: DP.coeffs(U, M, pU, pM, coef)  # noqa: E731
         else:            # the M-block gradient pass runs over R^T

@@ -173,3 +173,52 @@ def test_not_spd_row_fp32(ctx):
     Xg = X.cpu().numpy()
     assert np.all(np.isnan(Xg[0])) and np.all(np.isnan(Xg[2]))
     np.testing.assert_allclose(Xg[1], [1.0, 1.0, 1.0], rtol=1e-6)
+
+
+@pytest.mark.parametrize("n_f,ld", [(15, 15), (16, 16), (50, 64), (63, 63), (100, 100), (100, 104),
+                                    (127, 128), (143, 144)])
+def test_split_copy_matches_the_split_in_the_loop(ctx, n_f, ld):
+    """A planned FP32 half-sweep splits the fixed side once into a copy;
+    fold-in (no plan) splits each gathered row in the Gram loop.  Whole rows
+    (no chunk splits, no dual bins) give the same bits either way, including
+    positions past the end of a chunk (rows of 1..200 ratings)."""
+    from paper_1508_03110_amd.solver import DeviceProblem, fold_in
+    P = problem(n_f, seed=60 + n_f, n_u=70)
+    DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32, ld=ld)
+    assert DP.R.info()["split_rows"] == 0
+    DP.R.set_split_copy(1)
+    Y = DP.pack(np.zeros((P.n_u, P.n_f)), r32(P.M0))
+    X = torch.full((P.n_u, ld), float("nan"), dtype=torch.float32, device=ctx.torch_device)
+    DP.sweep("U", DP.M(Y), X)
+    M = DP.M(Y)[:, :n_f].contiguous()
+    U, st = fold_in(ctx, M, P.lam, P.R, n_f)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    assert torch.equal(X[:, :n_f], U[:, :n_f])
+    ref = oracle.half_sweep(P.R, r32(P.M0), P.lam)
+    assert rowrel(X[:, :n_f].cpu().numpy().astype(np.float64), ref) <= 1e-4
+
+
+@pytest.mark.parametrize("n_f", [50, 100])
+@pytest.mark.parametrize("chunk,dual", [(0, 0), (32, 0), (40, 30), (0, 62)])
+def test_split_copy_on_and_off_agree_bitwise(ctx, n_f, chunk, dual):
+    """The planned half-sweep with and without the split copy: rows cut over
+    chunks (partial Grams summed by the second stage), dual-form bins beside
+    the n_f x n_f launch, the fused gradient; every output bit equal."""
+    from paper_1508_03110_amd.solver import DeviceProblem
+    P = problem(n_f, seed=80 + n_f, long_rows=True)
+    DP = DeviceProblem(ctx, P.R, P.Rt, P.n_f, P.lam, torch.float32, chunk=chunk)
+    if dual:
+        DP.R.set_dual(dual)
+    x = DP.pack(r32(P.U0), r32(P.M0))
+    outs = []
+    for mode in (0, 1):
+        DP.R.set_split_copy(mode)
+        X = torch.full((P.n_u, DP.ld), float("nan"), dtype=torch.float32, device=ctx.torch_device)
+        G = torch.zeros((P.n_u, DP.ld), dtype=torch.float32, device=ctx.torch_device)
+        DP.sweep("U", DP.M(x), X, X_at=DP.U(x), grad_out=G)
+        outs.append((X, G))
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    ref = oracle.half_sweep(P.R, r32(P.M0), P.lam)
+    assert rowrel(outs[1][0][:, :n_f].cpu().numpy().astype(np.float64), ref) <= 1e-4
