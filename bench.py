@@ -803,7 +803,7 @@ def compact(res, full_path):
 def gather_probe(reps=10):
     """How much of each gather-bound phase is the gathers' trip beyond L2:
     the coefficient pass, the M-block gradient and both half-sweeps (length
-    bound 78 for users) at the 20M-rating shape, timed with the real rating
+    bound 78 and the split copy for users) at the 20M-rating shape, timed with the real rating
     ids and with every id folded into [0, 64) (same work and access count,
     every gathered row an L2 hit; the results of the folded runs are not
     used), and the M-block gradient with the real ids over a plan cut at 8
@@ -830,7 +830,7 @@ def gather_probe(reps=10):
 
     P = synth.c1_ml20m()
     ctx = Context(0)
-    out = {"workload": "20M-rating shape, n_f=100, FP32, user bound 78", "reps": reps}
+    out = {"workload": "20M-rating shape, n_f=100, FP32, user bound 78, user split copy", "reps": reps}
     for mode in ("real_ids", "ids_folded_into_64_rows"):
         R, Rt = P.R, P.Rt
         if mode != "real_ids":
@@ -839,6 +839,7 @@ def gather_probe(reps=10):
                            Rt.values)
         DP = DeviceProblem(ctx, R, Rt, P.n_f, P.lam, torch.float32)
         DP.R.set_dual(78)
+        DP.R.set_split_copy(1)
         x = DP.pack(P.U0.astype(np.float32), P.M0.astype(np.float32))
         p = torch.empty_like(x).normal_(0.0, 0.01)
         g = DP.zeros()
