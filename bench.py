@@ -787,6 +787,8 @@ def compact(res, full_path):
                             "sweep_U_tflops": _r(c2["sweep_U_tflops_eager"]),
                             "dual_max": {k: v["best"].get("dual_max") for k, v in
                                          c2.get("tuning", {}).items()},
+                            "split_copy": {k: v["best"].get("split_copy") for k, v in
+                                           c2.get("tuning", {}).items()},
                             "grad_slices": c2.get("tuning", {}).get("M", {}).get("best", {})
                                              .get("grad_slices"),
                             "phase_ms": {k: _r(v) for k, v in
@@ -929,19 +931,14 @@ def main():
     # length bins of the half-sweeps: the dual-form bound of each plan, by timing
     from paper_1508_03110_amd import tune
     x_t = DP.pack(U0, M0)
-    bins, splits = {}, {}
+    bins = {}
     fixed = [int(v) for v in args.dual.split(",")] if args.dual else None
     for k, (side, Y, n) in enumerate((("U", DP.M(x_t), P.n_u), ("M", DP.U(x_t), P.n_m))):
         X_t = torch.empty((n, DP.ld), dtype=torch.float32, device=ctx.torch_device)
         cands = (fixed[k],) if fixed else tune.DUAL_CANDIDATES
-        bins[side] = tune.tune_dual(DP, side, Y, X_t, candidates=cands)
-        log("length bins %s: %s" % (side, bins[side]))
-        if args.split_copy is not None:
-            (DP.R if side == "U" else DP.Rt).set_split_copy(int(args.split_copy.split(",")[k]))
-            splits[side] = {"best": {"split_copy": int(args.split_copy.split(",")[k])}, "trials": []}
-        else:
-            splits[side] = tune.tune_split_copy(DP, side, Y, X_t)
-        log("split copy %s: %s" % (side, splits[side]))
+        smodes = (int(args.split_copy.split(",")[k]),) if args.split_copy is not None else None
+        bins[side] = tune.tune_dual(DP, side, Y, X_t, candidates=cands, split_modes=smodes)
+        log("length bins and split copy %s: %s" % (side, bins[side]))
         del X_t
     # the M-block gradient's plan: cut at column slices of the user rows or not
     X_t = torch.empty((P.n_m, DP.ld), dtype=torch.float32, device=ctx.torch_device)
@@ -984,7 +981,7 @@ def main():
                 "kernel": "U half-sweep: sweep_chunks_kernel<float,7> + sweep_dual_kernel bins",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": profiled_traffic(bins["U"]["best"]["dual_max"], splits["U"]["best"]["split_copy"]),
+                "traffic": profiled_traffic(bins["U"]["best"]["dual_max"], bins["U"]["best"]["split_copy"]),
                 "flops_per_launch": fU, "launch_ms": round(phases["sweep_U"], 4),
                 "eq3_flops_per_launch": fU3,
                 "frac_eq3_count": round(fU3 / tU / 1e12 / PEAK_FP32_TFLOPS, 4),
@@ -1020,8 +1017,7 @@ def main():
         "length_bins": {k: v["best"] for k, v in bins.items()},
         "length_bin_trials": {k: v["trials"] for k, v in bins.items()},
         "grad_slices": gslices,
-        "split_copy": {k: v["best"]["split_copy"] for k, v in splits.items()},
-        "split_copy_trials": {k: v["trials"] for k, v in splits.items()},
+        "split_copy": {k: v["best"]["split_copy"] for k, v in bins.items()},
         "f": solver.f,
         "restarts": solver.restarts,
         "safeguards": solver.safeguards,

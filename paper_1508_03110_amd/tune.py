@@ -10,8 +10,8 @@ both algorithms) over a small grid of launch shapes and keeps the fastest:
 With that plan it then picks the length bins of the half-sweep: rows of at
 most `dual_max` ratings take the dual form (an n_i x n_i system, one kernel
 instance per 16-wide tile count), the rest the n_f x n_f form; candidates
-0 (off) and 16 b - 2 for b = 1 .. 6 tiles; and, in FP32, whether the
-n_f x n_f form gathers a split copy of the fixed side.  Last it picks the persistent
+0 (off) and 16 b - 2 for b = 1 .. 6 tiles, each timed (in FP32) with and
+without the split copy of the fixed side for the n_f x n_f form.  Last it picks the persistent
 grid of the orientation's streaming pass (coefficients for R, gradient for
 R^T), whose per-chunk work is small enough for workgroup dispatch to matter,
 and whether the M-block gradient takes a plan of R^T cut at column slices
@@ -46,32 +46,27 @@ def _best_ms(fn, reps):
 DUAL_CANDIDATES = (0, 14, 30, 46, 62, 78, 94)
 
 
-def tune_dual(DP, side: str, Y, X, reps: int = 3, candidates=DUAL_CANDIDATES) -> dict:
-    """Pick the dual-form length bound of one orientation's plan by timing its
-    half-sweep (Y: fixed side, X: output buffer); leaves the best one set."""
+def tune_dual(DP, side: str, Y, X, reps: int = 3, candidates=DUAL_CANDIDATES,
+              split_modes=None) -> dict:
+    """Pick the dual-form length bound of one orientation's plan together
+    with (FP32) whether its n_f x n_f form gathers a split copy of the fixed
+    side, by timing the half-sweep for every pair (Y: fixed side, X: output
+    buffer); leaves the best pair set.  split_modes: the split-copy settings
+    to try (default: off and on in FP32, the plan's default otherwise)."""
     A = DP.R if side == "U" else DP.Rt
+    if split_modes is None:
+        split_modes = (0, 1) if DP.dtype == torch.float32 else (-1,)
     trials = []
     for m in candidates:
         if m > 0 and m > A.info()["chunk"]:
             continue
         A.set_dual(m)
-        trials.append({"dual_max": m, "dual_rows": A.info()["dual_rows"],
-                       "ms": round(_best_ms(lambda: DP.sweep(side, Y, X), reps), 4)})
+        for sc in split_modes:
+            A.set_split_copy(sc)
+            trials.append({"dual_max": m, "split_copy": sc, "dual_rows": A.info()["dual_rows"],
+                           "ms": round(_best_ms(lambda: DP.sweep(side, Y, X), reps), 4)})
     best = min(trials, key=lambda t: t["ms"])
     A.set_dual(best["dual_max"])
-    return {"best": best, "trials": trials}
-
-
-def tune_split_copy(DP, side: str, Y, X, reps: int = 3) -> dict:
-    """FP32: time one orientation's half-sweep with and without the split
-    copy of the fixed side (fewer instructions per rating against wider
-    gathered rows); leaves the faster one set."""
-    A = DP.R if side == "U" else DP.Rt
-    trials = []
-    for mode in (0, 1):
-        A.set_split_copy(mode)
-        trials.append({"split_copy": mode, "ms": round(_best_ms(lambda: DP.sweep(side, Y, X), reps), 4)})
-    best = min(trials, key=lambda t: t["ms"])
     A.set_split_copy(best["split_copy"])
     return {"best": best, "trials": trials}
 
@@ -122,10 +117,8 @@ def tune(DP, x, reps: int = 2, chunk_factors=(1.0, 0.25), grids_per_cu=(0, 4, 8,
         best = min(trials, key=lambda t: t["ms"])
         A.replan(best["chunk"], best["grid"], 0)
         dual = tune_dual(DP, side, Y, X, reps=reps)
-        best = dict(best, dual_max=dual["best"]["dual_max"], dual_ms=dual["best"]["ms"])
-        if DP.dtype == torch.float32:
-            sc = tune_split_copy(DP, side, Y, X, reps=reps)
-            best = dict(best, split_copy=sc["best"]["split_copy"], split_copy_ms=sc["best"]["ms"])
+        best = dict(best, dual_max=dual["best"]["dual_max"], split_copy=dual["best"]["split_copy"],
+                    dual_ms=dual["best"]["ms"])
         if side == "U":  # the coefficient pass runs over R
             run = lambda: DP.coeffs(U, M, pU, pM, coef)  # noqa: E731
         else:            # the M-block gradient pass runs over R^T
