@@ -134,11 +134,15 @@ def c1():
 
 @pytest.fixture(scope="module")
 def c1_dev(ctx, c1):
-    """Default plans with the benchmark's usual length bins: users with 20..78
-    ratings (67,275 rows) in the dual form; no item has fewer than 79."""
+    """Default plans with the benchmark's usual choices: users with 20..78
+    ratings (67,275 rows) in the dual form (no item has fewer than 79), the
+    user half-sweep over the split copy of M, the M-block gradient over the
+    plan of R^T cut at 8 user slices."""
     from paper_1508_03110_amd.solver import DeviceProblem
     DP = DeviceProblem(ctx, c1.R, c1.Rt, c1.n_f, c1.lam, torch.float32)
     DP.R.set_dual(78)
+    DP.R.set_split_copy(1)
+    DP.Rt.set_grad_slices(8)
     assert DP.R.info()["dual_rows"] == 67275
     return DP
 
@@ -192,7 +196,9 @@ def test_ml20m_shape_als_ncg_trajectory(ctx, c1, c1_dev, mode):
 def test_ml20m_shape_full_passes(ctx, c1, c1_dev):
     """One coefficient pass and one gradient (both blocks, f and ||g||^2) over
     all 20,000,263 ratings in the default plans (8192-rating chunks, 315
-    split item rows) against the FP64 oracle on the same FP32 inputs:
+    split item rows; the M block over the plan cut at 8 user slices, then
+    again over the ordinary plan) against the FP64 oracle on the same FP32
+    inputs:
     coefficients within 1e-6 of the largest, gradient within 1e-5 relative
     (Frobenius, per block), f and ||g||^2 within 1e-6 and 1e-5."""
     P, DP = c1, c1_dev
@@ -222,3 +228,43 @@ def test_ml20m_shape_full_passes(ctx, c1, c1_dev):
     fg, gg = out.cpu().tolist()
     assert fg == pytest.approx(f, rel=1e-6)
     assert gg == pytest.approx(float(np.sum(gU ** 2) + np.sum(gM ** 2)), rel=1e-5)
+    # the same gradient over the ordinary plans of both orientations
+    try:
+        DP.Rt.set_grad_slices(0)
+        g8 = DP.zeros()
+        out8 = torch.zeros(2, dtype=torch.float64, device=dev)
+        DP.gradient(DP.U(x), DP.M(x), DP.U(g8), DP.M(g8), out8)
+        torch.cuda.synchronize()
+    finally:
+        DP.Rt.set_grad_slices(8)
+    for got, want in ((DP.U(g8), gU), (DP.M(g8), gM)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want)
+    fg8, gg8 = out8.cpu().tolist()
+    assert fg8 == pytest.approx(f, rel=1e-6)
+    assert gg8 == pytest.approx(float(np.sum(gU ** 2) + np.sum(gM ** 2)), rel=1e-5)
+
+
+def test_ml20m_shape_split_copy_is_bitwise(ctx, c1, c1_dev):
+    """Both half-sweeps over all 20,000,263 ratings (8192-rating chunks, split
+    rows on both sides, the fused gradient on the user side) with and without
+    the split copy of the fixed side: every output bit equal."""
+    P, DP = c1, c1_dev
+    dev = ctx.torch_device
+    x = DP.pack(P.U0.astype(np.float32), P.M0.astype(np.float32))
+    for side, A, Y, n in (("U", DP.R, DP.M(x), P.n_u), ("M", DP.Rt, DP.U(x), P.n_m)):
+        outs = []
+        try:
+            for mode in (0, 1):
+                A.set_split_copy(mode)
+                X = torch.empty((n, DP.ld), dtype=torch.float32, device=dev)
+                G = torch.empty((n, DP.ld), dtype=torch.float32, device=dev) if side == "U" else None
+                DP.sweep(side, Y, X, X_at=DP.U(x) if side == "U" else None, grad_out=G)
+                outs.append((X, G))
+            torch.cuda.synchronize()
+        finally:
+            A.set_split_copy(1 if side == "U" else -1)
+        print("split copy", side, flush=True)
+        assert torch.equal(outs[0][0], outs[1][0])
+        if side == "U":
+            assert torch.equal(outs[0][1], outs[1][1])
