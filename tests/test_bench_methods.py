@@ -80,7 +80,12 @@ def _full_result():
         "fold_in": {"continuous_batching": {"rates": rates},
                     "one_request_per_launch": {"rates": rates}},
         "reduced_precision": c3,
+        "length_bins": {"U": {"dual_max": 78, "split_copy": 1}, "M": {"dual_max": 62, "split_copy": 0}},
+        "grad_slices": {"best": {"slices": 8, "ms": 0.7}, "trials": [{"slices": 0, "ms": 1.1}]},
+        "split_copy": {"U": 1, "M": 0},
         "scale_1e9": {"als": {"ms_per_sweep": 100.0}, "sweep_U_tflops_eager": 31.5,
+                      "tuning": {"U": {"best": {"dual_max": 46, "split_copy": 1}},
+                                 "M": {"best": {"dual_max": 0, "split_copy": 0, "grad_slices": 0}}},
                       "als_ncg": {"ms_per_iteration": 280.0, "ratings_per_s": 7e9,
                                   "phase_ms_eager_step": {"sweep_U": 99.0}},
                       "speedup_vs_gnorm": {"curve": curve,
@@ -103,3 +108,31 @@ def test_compact_line_keeps_the_headline_and_fits_the_log_tail():
     assert d["reduced_precision"]["bf16_refined_nf128"]["rmse"] == 0.8
     assert d["scale_1e9"]["als_ncg_ms_per_iteration"] == 280.0
     assert d["value"] == pytest.approx(res["value"], rel=1e-5)
+    # the plan choices behind the numbers
+    assert d["dual_max"] == {"U": 78, "M": 62}
+    assert d["split_copy"] == {"U": 1, "M": 0} and d["grad_slices"] == 8
+    assert d["scale_1e9"]["split_copy"] == {"U": 1, "M": 0}
+    assert d["scale_1e9"]["grad_slices"] == 0
+
+
+def test_profiled_traffic_matches_hash_bound_and_split_copy(tmp_path, monkeypatch):
+    """The roofline's traffic is taken only from a TRAFFIC line of the same
+    kernel sources, length bound and split-copy choice (a line without the
+    split-copy key stands for the split in the loop)."""
+    (tmp_path / "profiles").mkdir()
+    lines = [
+        'TRAFFIC {"dual_max": 78, "split_copy": 1, "source_hash": "h1", "bytes": 11}',
+        'TRAFFIC {"dual_max": 78, "split_copy": 0, "source_hash": "h1", "bytes": 12}',
+        'TRAFFIC {"dual_max": 62, "source_hash": "h1", "bytes": 13}',
+        'TRAFFIC {"dual_max": 62, "split_copy": 1, "source_hash": "old", "bytes": 14}',
+    ]
+    (tmp_path / "profiles" / "sweep_chunks_f32_nf100_ml20m_shape.md").write_text(
+        "text\n" + "\n".join("    " + x for x in lines) + "\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h1")
+    assert bench.profiled_traffic(78, 1) == 11
+    assert bench.profiled_traffic(78, 0) == 12
+    assert bench.profiled_traffic(78) == 12
+    assert bench.profiled_traffic(62, 0) == 13
+    assert bench.profiled_traffic(62, 1) is None  # taken on other sources
+    assert bench.profiled_traffic(94, 1) is None
