@@ -45,7 +45,7 @@ def problem(seed, n_f, n_u=90, n_m=70):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("n_slices,chunk", [(1, 0), (3, 0), (8, 0), (8, 8), (16, 0), (40, 4)])
-@pytest.mark.parametrize("n_f", [20, 50, 100])
+@pytest.mark.parametrize("n_f", [20, 50, 100, 140])
 def test_sliced_gradient_matches_oracle(ctx, dtype, n_slices, chunk, n_f):
     """Both blocks through sliced plans of R and R^T: slices with no ratings
     of a row, rows in one slice only, empty rows, pieces cut further by a

@@ -175,8 +175,8 @@ def test_not_spd_row_fp32(ctx):
     np.testing.assert_allclose(Xg[1], [1.0, 1.0, 1.0], rtol=1e-6)
 
 
-@pytest.mark.parametrize("n_f,ld", [(15, 15), (16, 16), (50, 64), (63, 63), (100, 100), (100, 104),
-                                    (127, 128), (143, 144)])
+@pytest.mark.parametrize("n_f,ld", [(15, 15), (16, 16), (40, 40), (50, 64), (63, 63), (70, 72),
+                                    (90, 90), (100, 100), (100, 104), (127, 128), (143, 144)])
 def test_split_copy_matches_the_split_in_the_loop(ctx, n_f, ld):
     """A planned FP32 half-sweep splits the fixed side once into a copy;
     fold-in (no plan) splits each gathered row in the Gram loop.  Whole rows
